@@ -1,0 +1,204 @@
+"""Benchmark: VT/VV/TT relation entries per second on one MI355X.
+
+One step = every cluster of the 128^3 Kuhn lattice (2,097,152 vertices,
+12,290,298 tetrahedra, 2048 Morton clusters of 1024 vertices) built into HBM
+with all three relations in one batched persistent launch.  The mesh streams
+are resident in HBM before timing starts; copies to the host are not part of a
+step.  Prints one JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def output_bytes(entries: int, nv: int, nt: int, ncl: int) -> int:
+    """Bytes a step must write: entries, offsets (VT, VV per vertex row + 1 per
+    cluster, TT per tetrahedron row + 1 per cluster), row ids (vertex rows once,
+    tetrahedron rows) and an 8-word header per block."""
+    words = entries + (2 * nv + 2 * ncl) + (nt + ncl) + nv + nt + 8 * ncl
+    return 4 * words
+
+
+def cpu_baseline(mesh, budget_s: float = 15.0):
+    """The oracle as it stands, single-threaded, on the first clusters of the
+    same mesh until about budget_s seconds of block building."""
+    import oracle
+    t0 = time.perf_counter()
+    orc = oracle.Oracle.of(mesh)
+    t_setup = time.perf_counter() - t0
+    entries = 0
+    nclus = 0
+    t1 = time.perf_counter()
+    for k in range(mesh.nclusters):
+        for rel in (1, 2, 4):
+            _, _, e = orc.block(k, rel)
+            entries += len(e)
+        nclus += 1
+        if time.perf_counter() - t1 > budget_s:
+            break
+    dt = time.perf_counter() - t1
+    return {
+        "value": entries / dt, "unit": "entries/s", "cores": 1, "kind": "oracle",
+        "sample": "first %d of %d clusters, VT+VV+TT blocks, %.1f s of block building; "
+                  "global VT/owner setup %.2f s excluded" % (nclus, mesh.nclusters, dt, t_setup),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--block-threads", type=int, default=0)
+    ap.add_argument("--lds-bytes", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (clusters are independent; "
+              "see the sharding note in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import meshgen
+    from paper_2507_15230_amd import gale
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+
+    log("generating config", args.config)
+    mesh = meshgen.config(args.config)
+    nv, nt, ncl = mesh.nv, mesh.nt, mesh.nclusters
+    ids = np.arange(ncl, dtype=np.int32)
+
+    ctx = gale.Context(device=0, mode="direct", form="batched", block_threads=args.block_threads,
+                       lds_bytes=args.lds_bytes, stream=stream.cuda_stream)
+    log("loading")
+    ctx.load(mesh.tets, mesh.cluster, ncl)
+    st0 = ctx.stats()
+    mesh_bytes = st0["device_mesh_bytes"]
+
+    def one_round(k):
+        tks = [ctx.build(ids, 7, "batched") for _ in range(k)]
+        for t in tks:
+            ctx.poll(t)
+        return tks
+
+    # warmup: fills the buffer pool with as many output buffers as timed steps
+    log("warmup")
+    for _ in range(max(1, args.warmup)):
+        for t in one_round(args.steps):
+            ctx.release(t)
+    e_before = ctx.stats()["entries_built"]
+
+    # timed region: K steps back to back, HIP events on the launch stream
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tks = []
+    for i in range(args.steps):
+        starts[i].record(stream)
+        tks.append(ctx.build(ids, 7, "batched"))
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for t in tks:
+        ctx.poll(t)
+    entries_step = (ctx.stats()["entries_built"] - e_before) // args.steps
+    for t in tks:
+        ctx.release(t)
+    ev_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    ms_kernel = float(np.mean(ev_ms))
+    ms_step = wall * 1000.0 / args.steps
+    value = entries_step / (ms_step / 1000.0)
+    alg_bytes = mesh_bytes + output_bytes(entries_step, nv, nt, ncl)
+    achieved = alg_bytes / (ms_kernel / 1000.0) / 1e9
+
+    plain = None
+    if not args.no_plain:
+        log("plain per-cluster launches")
+        pctx = gale.Context(device=0, mode="direct", form="plain", block_threads=args.block_threads,
+                            lds_bytes=args.lds_bytes, stream=stream.cuda_stream)
+        pctx.load(mesh.tets, mesh.cluster, ncl)
+        for t in [pctx.build(ids, 7, "plain")]:
+            pctx.poll(t)
+            pctx.release(t)
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        t = pctx.build(ids, 7, "plain")
+        pctx.poll(t)
+        pdt = time.perf_counter() - p0
+        pctx.release(t)
+        pctx.close()
+        plain = {"value": entries_step / pdt, "unit": "entries/s", "launches": 3 * ncl,
+                 "ms_per_pass": pdt * 1000.0}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(mesh)
+
+    st = ctx.stats()
+    ctx.close()
+    out = {
+        "metric": "VT/VV/TT relation entries/s",
+        "value": value,
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": "128^3 Kuhn lattice (2,097,152 vertices, 12,290,298 tetrahedra), seed-permuted, "
+                        "2048 Morton clusters of 1024 vertices; VT+VV+TT for every cluster in one "
+                        "batched persistent launch" if args.config == 2 else "config %d" % args.config,
+            "config_index": args.config,
+            "seed": 0,
+            "entries_per_step": int(entries_step),
+            "clusters": ncl,
+            "form": "batched",
+            "block_threads": st0.get("block_threads", None) or args.block_threads or 256,
+            "load_seconds": st0["load_seconds"],
+            "global_path_blocks_per_step": int(st["global_path_blocks"] // max(1, st["requests"])),
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "alg_bytes_per_launch": int(alg_bytes), "kernel_ms": ms_kernel,
+        },
+        "cpu_baseline": cpu,
+        "plain": plain,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+// gale_ctx.h -- the context object and the runtime's internal types.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <list>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "gale_host.h"
+
+namespace gale {
+
+struct Buf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    bool pinned = false;
+};
+
+// Grow-only pool of device or pinned host buffers, reused by size so that
+// repeated requests of the same shape allocate nothing.
+struct Pool {
+    bool pinned = false;
+    std::mutex mu;
+    std::vector<Buf *> all, free_list;
+    Buf *acquire(size_t bytes, hipError_t *err);
+    void release(Buf *b);
+    void clear();
+};
+
+struct BlockLoc {
+    Buf *buf;
+    int64_t word;
+};
+
+// One set of work items built together, with its buffers.
+struct Batch {
+    std::vector<WorkItem> items;
+    int64_t out_words = 0;
+    Buf *out = nullptr, *dev_items = nullptr, *dev_hdr = nullptr, *ws = nullptr;
+    Buf *host_items = nullptr, *host_hdr = nullptr, *host_out = nullptr;
+    std::vector<Buf *> extra;           // rebuild outputs owned by this batch
+    std::vector<int32_t> hdr;           // 8 words per item, after finalize
+    std::vector<BlockLoc> loc;          // where each item's block lives, after finalize
+    std::vector<int64_t> host_word;     // host copy offsets
+    bool host_ready = false;
+};
+
+struct Ticket {
+    Batch batch;
+    uint32_t mask = 0;
+    bool host = false;
+    bool ready = false;
+    gale_status status = GALE_OK;
+    hipEvent_t done = nullptr;
+    std::unordered_map<int32_t, std::vector<int>> by_cluster;
+};
+
+// ---- serving -------------------------------------------------------------
+using Clock = std::chrono::steady_clock;
+
+struct ServeReq;
+
+struct CacheEntry {
+    int32_t cluster = 0;
+    uint32_t mask = 0;
+    int64_t off = 0;        // bytes into the arena
+    int64_t bytes = 0;      // bytes allocated
+    int state = 0;          // 0 = building, 1 = resident
+    int pins = 0;           // requests holding it (waiting or copying)
+    int32_t cap_vv = 0, cap_tt = 0;
+    int32_t hdr[8] = {0};
+    bool in_lru = false;
+    std::list<int64_t>::iterator lru_it;
+    std::vector<ServeReq *> waiters;
+};
+
+struct ServeReq {
+    uint64_t id = 0;
+    std::vector<int32_t> clusters;
+    uint32_t mask = 0;
+    Clock::time_point t_submit, t_admit, t_built, t_ready;
+    int waiting = 0;
+    bool admitted = false, copying = false, ready = false, released = false;
+    gale_status status = GALE_OK;
+    std::vector<int64_t> keys;          // cache keys held (pinned)
+    Buf *host = nullptr;
+    std::vector<int64_t> host_word;     // per cluster (same order as clusters)
+    std::vector<CacheEntry> snap;       // header / capacities of each block at copy time
+    hipEvent_t copy_done = nullptr;
+};
+
+struct Slot {
+    bool busy = false;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    Batch batch;
+    std::vector<int64_t> keys;          // cache keys built by this batch, per item
+};
+
+struct Serve {
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool stop = false;
+    std::deque<ServeReq *> pending;
+    std::unordered_map<uint64_t, ServeReq *> reqs;
+    std::unordered_map<int64_t, CacheEntry> cache;
+    std::list<int64_t> lru;             // unpinned resident keys, least recent first
+    std::map<int64_t, int64_t> free_map;  // arena free ranges offset -> bytes
+    void *arena = nullptr;
+    int64_t arena_bytes = 0, resident_bytes = 0;
+    std::vector<Slot> slots;
+    std::vector<ServeReq *> copying;
+    hipStream_t copy_stream = nullptr;
+    // statistics
+    uint64_t hits = 0, misses = 0, evictions = 0, batches = 0, batch_clusters = 0;
+    uint64_t admissions = 0, depth_sum = 0;
+    int32_t depth_max = 0;
+    std::vector<double> lat_us, q_us, b_us, c_us;
+};
+
+}  // namespace gale
+
+struct gale_ctx {
+    gale_config cfg{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool poisoned = false;
+    int num_cus = 0, occupancy = 1, persistent_grid = 1, block_threads = 256;
+    int64_t lds_budget = 0;
+    // mesh
+    bool loaded = false;
+    int32_t nv = 0, ncl = 0;
+    int64_t nt = 0, stream_tets = 0;
+    uint64_t mesh_bytes = 0;
+    double load_seconds = 0;
+    std::vector<gale::ClusterMeta> meta;
+    int32_t *d_tets = nullptr, *d_tid = nullptr, *d_lverts = nullptr;
+    gale::ClusterMeta *d_meta = nullptr;
+    // pools and tickets
+    gale::Pool dev_pool, pin_pool;
+    std::mutex direct_mu, tick_mu;
+    std::unordered_map<uint64_t, gale::Ticket *> tickets;
+    uint64_t next_ticket = 0;
+    // counters
+    std::atomic<uint64_t> n_requests{0}, n_blocks{0}, n_entries{0}, n_launches{0}, n_overflow{0},
+        n_global_blocks{0}, n_delivered{0}, n_bytes_d2h{0};
+    gale::Serve serve;
+};
+
+namespace gale {
+gale_status fail(gale_status s, const std::string &msg);
+int32_t default_cap_tt(const ClusterMeta &m);
+int64_t lay_out_items(const gale_ctx *ctx, std::vector<WorkItem> &items, int64_t out_base_word);
+int64_t workspace_bytes(const gale_ctx *ctx, const std::vector<WorkItem> &items, int *n_global);
+gale_status launch_batch(gale_ctx *ctx, int form, int32_t *d_out, int32_t *d_hdr, const WorkItem *d_items,
+                         int nitems, int32_t *d_queue, char *d_ws, int64_t ws_stride, hipStream_t st);
+gale_status check_request(const gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t mask);
+
+gale_status serve_start(gale_ctx *ctx);
+void serve_stop(gale_ctx *ctx);
+gale_status serve_submit(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t mask, uint64_t *ticket);
+gale_status serve_poll(gale_ctx *ctx, uint64_t ticket, int64_t timeout_ns);
+gale_status serve_block(gale_ctx *ctx, uint64_t ticket, int32_t cluster, uint32_t rel, gale_csr *out);
+gale_status serve_release(gale_ctx *ctx, uint64_t ticket);
+void serve_stats(gale_ctx *ctx, gale_stats *out);
+void serve_reset_stats(gale_ctx *ctx);
+}  // namespace gale

@@ -1,0 +1,382 @@
+// gale_load.cpp -- host preparation of the per-cluster streams.
+//
+// The paper's initialization (Section 4.3) runs on the CPU: it builds, per
+// segment, the list of external tetrahedra and the interval arrays, and copies
+// them to GPU memory.  This is the same step for the per-cluster layout in
+// gale_layout.h:
+//   1. validate T and S;
+//   2. owner(t) = smallest cluster id among t's vertices (internal rule);
+//   3. star(C) = tetrahedra with a vertex in C, in ascending id (a stable
+//      counting sort by cluster over ascending tetrahedron ids);
+//   4. halo(C): a tetrahedron internal to C whose vertices include exactly one
+//      vertex of C has an opposite triangle with no vertex in C; the other
+//      tetrahedra on that triangle may lie outside star(C).  They are found by
+//      intersecting the (ascending) global VT lists of the triangle's vertices
+//      and appended as the halo, so that TT rows are complete;
+//   5. local vertex table = sorted distinct vertices of star, halo and C;
+//      stream tetrahedra are re-expressed in local ids.
+// Everything here is integer bookkeeping; no relation entry is produced.
+#include <algorithm>
+#include <atomic>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "gale_host.h"
+
+namespace gale {
+
+namespace {
+
+int num_threads() {
+    unsigned n = std::thread::hardware_concurrency();
+    if (n == 0) n = 4;
+    return (int)std::min<unsigned>(n, 32);
+}
+
+template <class F>
+void parallel_for(int64_t n, F f) {
+    const int P = num_threads();
+    if (n <= 4096 || P == 1) {
+        f(0, n, 0);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t chunk = (n + P - 1) / P;
+    for (int i = 0; i < P; ++i) {
+        const int64_t b = i * chunk, e = std::min<int64_t>(n, b + chunk);
+        if (b >= e) break;
+        th.emplace_back(f, b, e, i);
+    }
+    for (auto &t : th) t.join();
+}
+
+}  // namespace
+
+gale_status prepare_streams(int32_t nv, int64_t nt, const int32_t *tv, const int32_t *cl, int32_t ncl,
+                            HostStreams &out, std::string &err) {
+    if (nv < 0 || nt < 0 || ncl <= 0) {
+        err = "nv, nt must be >= 0 and nclusters >= 1";
+        return GALE_EINVAL;
+    }
+    if (nt > 0x3fffffffLL) {
+        err = "more than 2^30 tetrahedra";
+        return GALE_EINVAL;
+    }
+    if (nt > 0 && !tv) {
+        err = "tv is NULL";
+        return GALE_EINVAL;
+    }
+    if (nv > 0 && !cl) {
+        err = "cluster_of_vertex is NULL";
+        return GALE_EINVAL;
+    }
+    // 1. validate
+    std::atomic<int64_t> bad_t{-1};
+    parallel_for(nt, [&](int64_t b, int64_t e, int) {
+        for (int64_t t = b; t < e; ++t) {
+            const int32_t *q = tv + 4 * t;
+            bool ok = true;
+            for (int i = 0; i < 4 && ok; ++i) {
+                if (q[i] < 0 || q[i] >= nv) ok = false;
+                for (int j = 0; j < i && ok; ++j)
+                    if (q[i] == q[j]) ok = false;
+            }
+            if (!ok) {
+                int64_t expect = -1;
+                bad_t.compare_exchange_strong(expect, t);
+                return;
+            }
+        }
+    });
+    if (bad_t.load() >= 0) {
+        err = "tetrahedron " + std::to_string(bad_t.load()) + " has a vertex id out of range or a repeated vertex";
+        return GALE_EINVAL;
+    }
+    for (int32_t v = 0; v < nv; ++v) {
+        if (cl[v] < 0 || cl[v] >= ncl) {
+            err = "vertex " + std::to_string(v) + " has cluster id out of range";
+            return GALE_EINVAL;
+        }
+    }
+
+    // rows of every cluster: vertices in ascending id
+    std::vector<int64_t> voff(ncl + 1, 0);
+    for (int32_t v = 0; v < nv; ++v) voff[cl[v] + 1]++;
+    for (int32_t k = 0; k < ncl; ++k) voff[k + 1] += voff[k];
+    std::vector<int32_t> vrows(nv);
+    {
+        std::vector<int64_t> f(voff.begin(), voff.end() - 1);
+        for (int32_t v = 0; v < nv; ++v) vrows[f[cl[v]]++] = v;
+    }
+
+    // 2. owner and distinct clusters per tetrahedron
+    std::vector<int32_t> owner(nt);
+    parallel_for(nt, [&](int64_t b, int64_t e, int) {
+        for (int64_t t = b; t < e; ++t) {
+            const int32_t *q = tv + 4 * t;
+            int32_t o = cl[q[0]];
+            for (int i = 1; i < 4; ++i) o = std::min(o, cl[q[i]]);
+            owner[t] = o;
+        }
+    });
+
+    // 3. star(C): stable counting sort by cluster over ascending tetrahedron ids,
+    // per-thread counts so the fill stays in id order.
+    const int P = num_threads();
+    const int64_t chunk = (nt + P - 1) / std::max(P, 1);
+    std::vector<std::vector<int64_t>> cnt(P, std::vector<int64_t>(ncl, 0));
+    auto distinct = [&](int64_t t, int32_t *c4) -> int {
+        const int32_t *q = tv + 4 * t;
+        int n = 0;
+        for (int i = 0; i < 4; ++i) {
+            const int32_t k = cl[q[i]];
+            bool seen = false;
+            for (int j = 0; j < n; ++j) seen |= c4[j] == k;
+            if (!seen) c4[n++] = k;
+        }
+        return n;
+    };
+    {
+        std::vector<std::thread> th;
+        for (int i = 0; i < P; ++i) {
+            th.emplace_back([&, i] {
+                const int64_t b = i * chunk, e = std::min<int64_t>(nt, b + chunk);
+                int32_t c4[4];
+                for (int64_t t = b; t < e; ++t) {
+                    const int n = distinct(t, c4);
+                    for (int j = 0; j < n; ++j) cnt[i][c4[j]]++;
+                }
+            });
+        }
+        for (auto &t : th) t.join();
+    }
+    std::vector<int64_t> soff(ncl + 1, 0);
+    for (int32_t k = 0; k < ncl; ++k) {
+        int64_t s = 0;
+        for (int i = 0; i < P; ++i) s += cnt[i][k];
+        soff[k + 1] = soff[k] + s;
+    }
+    std::vector<int32_t> star(soff[ncl]);
+    {
+        // start position of (thread i, cluster k)
+        for (int32_t k = 0; k < ncl; ++k) {
+            int64_t pos = soff[k];
+            for (int i = 0; i < P; ++i) {
+                const int64_t c = cnt[i][k];
+                cnt[i][k] = pos;
+                pos += c;
+            }
+        }
+        std::vector<std::thread> th;
+        for (int i = 0; i < P; ++i) {
+            th.emplace_back([&, i] {
+                const int64_t b = i * chunk, e = std::min<int64_t>(nt, b + chunk);
+                int32_t c4[4];
+                for (int64_t t = b; t < e; ++t) {
+                    const int n = distinct(t, c4);
+                    for (int j = 0; j < n; ++j) star[cnt[i][c4[j]]++] = (int32_t)t;
+                }
+            });
+        }
+        for (auto &t : th) t.join();
+    }
+    cnt.clear();
+    cnt.shrink_to_fit();
+
+    // 4. halo.  Global VT (lists ascending) for the triangles that need it.
+    std::vector<int64_t> vtoff(nv + 1, 0);
+    for (int64_t i = 0; i < 4 * nt; ++i) vtoff[tv[i] + 1]++;
+    for (int32_t v = 0; v < nv; ++v) vtoff[v + 1] += vtoff[v];
+    std::vector<int32_t> vt(4 * nt);
+    {
+        std::vector<int64_t> f(vtoff.begin(), vtoff.end() - 1);
+        for (int64_t t = 0; t < nt; ++t)
+            for (int i = 0; i < 4; ++i) vt[f[tv[4 * t + i]]++] = (int32_t)t;
+    }
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> halo_parts(P);
+    {
+        std::vector<std::thread> th;
+        for (int i = 0; i < P; ++i) {
+            th.emplace_back([&, i] {
+                const int64_t b = i * chunk, e = std::min<int64_t>(nt, b + chunk);
+                auto &outp = halo_parts[i];
+                for (int64_t t = b; t < e; ++t) {
+                    const int32_t *q = tv + 4 * t;
+                    const int32_t o = owner[t];
+                    int inC = 0, only = -1;
+                    for (int j = 0; j < 4; ++j)
+                        if (cl[q[j]] == o) { ++inC; only = j; }
+                    if (inC != 1) continue;
+                    int32_t f[3];
+                    int m = 0;
+                    for (int j = 0; j < 4; ++j)
+                        if (j != only) f[m++] = q[j];
+                    const int32_t *la = vt.data() + vtoff[f[0]], *lb = vt.data() + vtoff[f[1]],
+                                  *lc = vt.data() + vtoff[f[2]];
+                    const int64_t na = vtoff[f[0] + 1] - vtoff[f[0]], nb = vtoff[f[1] + 1] - vtoff[f[1]],
+                                  nc = vtoff[f[2] + 1] - vtoff[f[2]];
+                    int64_t x = 0, y = 0, z = 0;
+                    while (x < na && y < nb && z < nc) {
+                        const int32_t A = la[x], Bv = lb[y], Cv = lc[z];
+                        if (A == Bv && Bv == Cv) {
+                            if (A != (int32_t)t) {
+                                const int32_t *qq = tv + 4 * (int64_t)A;
+                                bool touches = false;
+                                for (int j = 0; j < 4; ++j) touches |= cl[qq[j]] == o;
+                                if (!touches) outp.emplace_back(o, A);
+                            }
+                            ++x; ++y; ++z;
+                            continue;
+                        }
+                        const int32_t mx = std::max(A, std::max(Bv, Cv));
+                        if (A < mx) ++x;
+                        if (Bv < mx) ++y;
+                        if (Cv < mx) ++z;
+                    }
+                }
+            });
+        }
+        for (auto &t : th) t.join();
+    }
+    vt.clear();
+    vt.shrink_to_fit();
+    vtoff.clear();
+    vtoff.shrink_to_fit();
+    std::vector<std::pair<int32_t, int32_t>> halo;
+    {
+        size_t tot = 0;
+        for (auto &h : halo_parts) tot += h.size();
+        halo.reserve(tot);
+        for (auto &h : halo_parts) {
+            halo.insert(halo.end(), h.begin(), h.end());
+            h.clear();
+            h.shrink_to_fit();
+        }
+        std::sort(halo.begin(), halo.end());
+        halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
+    }
+    std::vector<int64_t> hoff(ncl + 1, 0);
+    for (auto &p : halo) hoff[p.first + 1]++;
+    for (int32_t k = 0; k < ncl; ++k) hoff[k + 1] += hoff[k];
+
+    // 5. local tables and encoded streams, per cluster
+    out.meta.assign(ncl, ClusterMeta{});
+    std::vector<std::vector<int32_t>> ltab(ncl);
+    std::atomic<int32_t> next{0};
+    std::atomic<int> too_big{0};
+    {
+        std::vector<std::thread> th;
+        for (int i = 0; i < P; ++i) {
+            th.emplace_back([&] {
+                std::vector<int32_t> deg;
+                while (true) {
+                    const int32_t k = next.fetch_add(1);
+                    if (k >= ncl) break;
+                    auto &tab = ltab[k];
+                    const int64_t s0 = soff[k], s1 = soff[k + 1];
+                    const int64_t h0 = hoff[k], h1 = hoff[k + 1];
+                    tab.clear();
+                    tab.reserve((size_t)(4 * (s1 - s0 + h1 - h0) + voff[k + 1] - voff[k]));
+                    for (int64_t s = s0; s < s1; ++s)
+                        for (int j = 0; j < 4; ++j) tab.push_back(tv[4 * (int64_t)star[s] + j]);
+                    for (int64_t s = h0; s < h1; ++s)
+                        for (int j = 0; j < 4; ++j) tab.push_back(tv[4 * (int64_t)halo[s].second + j]);
+                    for (int64_t s = voff[k]; s < voff[k + 1]; ++s) tab.push_back(vrows[s]);
+                    std::sort(tab.begin(), tab.end());
+                    tab.erase(std::unique(tab.begin(), tab.end()), tab.end());
+                    ClusterMeta &m = out.meta[k];
+                    m.ns = (int32_t)(s1 - s0);
+                    m.nh = (int32_t)(h1 - h0);
+                    m.L = (int32_t)tab.size();
+                    m.nV = (int32_t)(voff[k + 1] - voff[k]);
+                    if ((int64_t)tab.size() > 0x7fffffffLL) too_big = 1;
+                    int64_t nnz = 0, nT = 0;
+                    deg.assign(m.nV, 0);
+                    for (int64_t s = s0; s < s1; ++s) {
+                        const int32_t t = star[s];
+                        if (owner[t] == k) ++nT;
+                        for (int j = 0; j < 4; ++j) {
+                            const int32_t v = tv[4 * (int64_t)t + j];
+                            if (cl[v] == k) {
+                                ++nnz;
+                                // row index = rank of v among C's vertices (ascending id)
+                                const int32_t *rb = vrows.data() + voff[k];
+                                const int64_t r = std::lower_bound(rb, rb + m.nV, v) - rb;
+                                deg[r]++;
+                            }
+                        }
+                    }
+                    if (nnz > 0x7fffffffLL) too_big = 1;
+                    m.nnzVT = (int32_t)nnz;
+                    m.nT = (int32_t)nT;
+                    int64_t capvv = 0;
+                    for (int32_t r = 0; r < m.nV; ++r) {
+                        const int64_t d = deg[r];
+                        int64_t c = std::min<int64_t>(d + 2, 3 * d);
+                        c = std::min<int64_t>(c, (int64_t)m.L - 1);
+                        capvv += std::max<int64_t>(c, 0);
+                    }
+                    if (capvv > 0x7fffffffLL) too_big = 1;
+                    m.cap_vv = (int32_t)capvv;
+                }
+            });
+        }
+        for (auto &t : th) t.join();
+    }
+    if (too_big.load()) {
+        err = "a cluster exceeds the 2^31 entries limit of one block";
+        return GALE_EINVAL;
+    }
+    int64_t tetn = 0, lvn = 0;
+    for (int32_t k = 0; k < ncl; ++k) {
+        out.meta[k].tet_off = tetn;
+        out.meta[k].lv_off = lvn;
+        tetn += (int64_t)out.meta[k].ns + out.meta[k].nh;
+        lvn += out.meta[k].L;
+    }
+    out.tets.assign((size_t)tetn * 4, 0);
+    out.tid.assign((size_t)tetn, 0);
+    out.lverts.assign((size_t)lvn, 0);
+    next = 0;
+    {
+        std::vector<std::thread> th;
+        for (int i = 0; i < P; ++i) {
+            th.emplace_back([&] {
+                while (true) {
+                    const int32_t k = next.fetch_add(1);
+                    if (k >= ncl) break;
+                    const auto &tab = ltab[k];
+                    const ClusterMeta &m = out.meta[k];
+                    for (int32_t l = 0; l < m.L; ++l) {
+                        const int32_t v = tab[l];
+                        out.lverts[m.lv_off + l] = cl[v] == k ? (int32_t)((uint32_t)v | 0x80000000u) : v;
+                    }
+                    auto local = [&](int32_t v) -> int32_t {
+                        return (int32_t)(std::lower_bound(tab.begin(), tab.end(), v) - tab.begin());
+                    };
+                    int64_t p = m.tet_off;
+                    for (int64_t s = soff[k]; s < soff[k + 1]; ++s, ++p) {
+                        const int32_t t = star[s];
+                        for (int j = 0; j < 4; ++j) out.tets[4 * p + j] = local(tv[4 * (int64_t)t + j]);
+                        out.tid[p] = owner[t] == k ? (int32_t)((uint32_t)t | 0x80000000u) : t;
+                    }
+                    for (int64_t s = hoff[k]; s < hoff[k + 1]; ++s, ++p) {
+                        const int32_t t = halo[s].second;
+                        for (int j = 0; j < 4; ++j) out.tets[4 * p + j] = local(tv[4 * (int64_t)t + j]);
+                        out.tid[p] = t;
+                    }
+                }
+            });
+        }
+        for (auto &t : th) t.join();
+    }
+    out.nv = nv;
+    out.nt = nt;
+    out.ncl = ncl;
+    return GALE_OK;
+}
+
+}  // namespace gale

@@ -1,0 +1,221 @@
+"""ctypes binding of the C ABI in include/gale.h (argument marshalling only).
+
+Every relation is built by the HIP kernels inside libgale.so; this module only
+converts numpy arrays to pointers and views back to numpy arrays.  Importing
+it without the built library raises an error: there is no other code path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgale.so")
+
+REL_VT, REL_VV, REL_TT, REL_ALL = 1, 2, 4, 7
+FORM_PLAIN, FORM_BATCHED = 0, 1
+MODE_DIRECT, MODE_SERVE = 0, 1
+
+OK, EINVAL, ENOMEM, EAGAIN, ENOENT, ESTATE, EDEVICE = 0, -1, -2, -3, -4, -5, -6
+_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EAGAIN", -4: "ENOENT", -5: "ESTATE", -6: "EDEVICE"}
+
+
+class GaleConfig(C.Structure):
+    _fields_ = [
+        ("device", C.c_int32), ("mode", C.c_int32), ("form", C.c_int32), ("block_threads", C.c_int32),
+        ("lds_bytes", C.c_int32), ("max_inflight", C.c_int32), ("cache_budget_bytes", C.c_uint64),
+        ("max_queue", C.c_int32), ("reserved", C.c_int32), ("hip_stream", C.c_void_p),
+    ]
+
+
+class GaleCsr(C.Structure):
+    _fields_ = [
+        ("cluster", C.c_int32), ("rel", C.c_uint32), ("nrows", C.c_int32), ("pad", C.c_int32),
+        ("nnz", C.c_int64), ("row_ids", C.POINTER(C.c_int32)), ("offsets", C.POINTER(C.c_int32)),
+        ("entries", C.POINTER(C.c_int32)),
+    ]
+
+
+class GaleStats(C.Structure):
+    _fields_ = [
+        ("nv", C.c_int32), ("nclusters", C.c_int32), ("nt", C.c_int64), ("stream_tets", C.c_int64),
+        ("device_mesh_bytes", C.c_uint64), ("load_seconds", C.c_double),
+        ("requests", C.c_uint64), ("blocks_built", C.c_uint64), ("entries_built", C.c_uint64),
+        ("kernel_launches", C.c_uint64), ("overflow_reruns", C.c_uint64), ("global_path_blocks", C.c_uint64),
+        ("cache_hits", C.c_uint64), ("cache_misses", C.c_uint64), ("evictions", C.c_uint64),
+        ("cache_bytes_resident", C.c_uint64), ("cache_budget", C.c_uint64),
+        ("entries_delivered", C.c_uint64), ("bytes_d2h", C.c_uint64), ("batches", C.c_uint64),
+        ("mean_batch_clusters", C.c_double), ("queue_depth_mean", C.c_double),
+        ("queue_depth_max", C.c_int32), ("pad", C.c_int32),
+        ("lat_p50_us", C.c_double), ("lat_p99_us", C.c_double), ("lat_mean_us", C.c_double),
+        ("lat_max_us", C.c_double), ("lat_count", C.c_uint64),
+        ("stage_queue_us", C.c_double), ("stage_build_us", C.c_double), ("stage_copy_us", C.c_double),
+    ]
+
+
+class GaleError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__("%s: %s (%s) %s" % (where, _NAMES.get(status, status), status, detail))
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgale.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libgale.so is not built (%s); run __graft_entry__.build()" % path)
+    lib = C.CDLL(path)
+    i32p = C.POINTER(C.c_int32)
+    vp = C.c_void_p
+    u64p = C.POINTER(C.c_uint64)
+    sig = {
+        "gale_create": ([C.POINTER(GaleConfig), C.POINTER(vp)], C.c_int32),
+        "gale_load": ([vp, C.c_int32, C.c_int64, i32p, i32p, C.c_int32], C.c_int32),
+        "gale_submit": ([vp, i32p, C.c_int32, C.c_uint32, u64p], C.c_int32),
+        "gale_build": ([vp, i32p, C.c_int32, C.c_uint32, C.c_int32, u64p], C.c_int32),
+        "gale_poll": ([vp, C.c_uint64, C.c_int64], C.c_int32),
+        "gale_block": ([vp, C.c_uint64, C.c_int32, C.c_uint32, C.POINTER(GaleCsr)], C.c_int32),
+        "gale_block_device": ([vp, C.c_uint64, C.c_int32, C.c_uint32, C.POINTER(GaleCsr)], C.c_int32),
+        "gale_release": ([vp, C.c_uint64], C.c_int32),
+        "gale_get_stats": ([vp, C.POINTER(GaleStats)], C.c_int32),
+        "gale_reset_stats": ([vp], C.c_int32),
+        "gale_stream": ([vp], vp),
+        "gale_strerror": ([C.c_int32], C.c_char_p),
+        "gale_last_error": ([], C.c_char_p),
+        "gale_destroy": ([vp], None),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _check(st: int, where: str):
+    if st != OK:
+        raise GaleError(st, where, _lib.gale_last_error().decode(errors="replace"))
+
+
+class Context:
+    """One library context (one device).  ``mode`` is "direct" or "serve";
+    ``form`` (direct mode) is "plain" or "batched"."""
+
+    def __init__(self, device: int = 0, mode: str = "direct", form: str = "batched", block_threads: int = 0,
+                 lds_bytes: int = 0, max_inflight: int = 0, cache_budget_bytes: int = 0, max_queue: int = 0,
+                 stream=None):
+        lib = load_library()
+        self._lib = lib
+        cfg = GaleConfig()
+        cfg.device = device
+        cfg.mode = {"direct": MODE_DIRECT, "serve": MODE_SERVE}[mode]
+        cfg.form = {"plain": FORM_PLAIN, "batched": FORM_BATCHED}[form]
+        cfg.block_threads = block_threads
+        cfg.lds_bytes = lds_bytes
+        cfg.max_inflight = max_inflight
+        cfg.cache_budget_bytes = cache_budget_bytes
+        cfg.max_queue = max_queue
+        cfg.hip_stream = stream
+        h = C.c_void_p()
+        _check(lib.gale_create(C.byref(cfg), C.byref(h)), "gale_create")
+        self._h = h
+        self.mode = mode
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.gale_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def stream(self) -> int:
+        return int(self._lib.gale_stream(self._h) or 0)
+
+    def load(self, tets, cluster, nclusters: int):
+        t, tp = _i32(np.asarray(tets).reshape(-1))
+        c, cp = _i32(cluster)
+        _check(self._lib.gale_load(self._h, int(c.shape[0]), int(t.shape[0] // 4), tp, cp, int(nclusters)),
+               "gale_load")
+
+    def submit(self, ids, mask: int = REL_ALL) -> int:
+        a, p = _i32(np.atleast_1d(ids))
+        tk = C.c_uint64()
+        _check(self._lib.gale_submit(self._h, p, int(a.shape[0]), int(mask), C.byref(tk)), "gale_submit")
+        return tk.value
+
+    def try_submit(self, ids, mask: int = REL_ALL):
+        """Like submit, but returns the status instead of raising (for EAGAIN)."""
+        a, p = _i32(np.atleast_1d(ids))
+        tk = C.c_uint64()
+        st = self._lib.gale_submit(self._h, p, int(a.shape[0]), int(mask), C.byref(tk))
+        return st, tk.value
+
+    def build(self, ids, mask: int = REL_ALL, form: str = "batched") -> int:
+        a, p = _i32(np.atleast_1d(ids))
+        tk = C.c_uint64()
+        f = {"plain": FORM_PLAIN, "batched": FORM_BATCHED}[form]
+        _check(self._lib.gale_build(self._h, p, int(a.shape[0]), int(mask), f, C.byref(tk)), "gale_build")
+        return tk.value
+
+    def poll(self, ticket: int, timeout_ns: int = -1) -> bool:
+        st = self._lib.gale_poll(self._h, C.c_uint64(ticket), int(timeout_ns))
+        if st == EAGAIN:
+            return False
+        _check(st, "gale_poll")
+        return True
+
+    def _view(self, fn, ticket, cluster, rel):
+        v = GaleCsr()
+        _check(fn(self._h, C.c_uint64(ticket), int(cluster), int(rel), C.byref(v)), fn.__name__)
+        return v
+
+    def block(self, ticket: int, cluster: int, rel: int):
+        """Host block as numpy copies (row_ids, offsets, entries)."""
+        v = self._view(self._lib.gale_block, ticket, cluster, rel)
+        n, z = v.nrows, v.nnz
+        rows = np.ctypeslib.as_array(v.row_ids, shape=(n,)).copy() if n else np.empty(0, np.int32)
+        offs = np.ctypeslib.as_array(v.offsets, shape=(n + 1,)).copy()
+        ents = np.ctypeslib.as_array(v.entries, shape=(z,)).copy() if z else np.empty(0, np.int32)
+        return rows, offs, ents
+
+    def block_device(self, ticket: int, cluster: int, rel: int) -> GaleCsr:
+        """Device view: raw device pointers and sizes."""
+        return self._view(self._lib.gale_block_device, ticket, cluster, rel)
+
+    def release(self, ticket: int):
+        _check(self._lib.gale_release(self._h, C.c_uint64(ticket)), "gale_release")
+
+    def stats(self) -> dict:
+        s = GaleStats()
+        _check(self._lib.gale_get_stats(self._h, C.byref(s)), "gale_get_stats")
+        return {name: getattr(s, name) for name, _ in GaleStats._fields_ if name != "pad"}
+
+    def reset_stats(self):
+        _check(self._lib.gale_reset_stats(self._h), "gale_reset_stats")
+
+
+def strerror(status: int) -> str:
+    return load_library().gale_strerror(int(status)).decode()

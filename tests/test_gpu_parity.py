@@ -1,0 +1,220 @@
+"""GPU parity: every block from the HIP path equals the oracle's, byte for
+byte (integer data, tolerance 0), through the C ABI."""
+import sys
+
+import numpy as np
+import pytest
+
+import meshgen
+import oracle
+from tests import pinlib
+
+pytestmark = pytest.mark.gpu
+
+REL = (1, 2, 4)
+
+
+def _gale():
+    from paper_2507_15230_amd import gale
+    return gale
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def compare_all(ctx, mesh, orc, ids=None, mask=7, ticket=None):
+    """Submit ids (default: all) and compare every requested block."""
+    gale = _gale()
+    ids = np.arange(mesh.nclusters, dtype=np.int32) if ids is None else np.asarray(ids, np.int32)
+    tk = ctx.submit(ids, mask) if ticket is None else ticket
+    bad = []
+    for k in np.unique(ids):
+        for rel in REL:
+            if not (mask & rel):
+                continue
+            got = ctx.block(tk, int(k), rel)
+            exp = orc.block(int(k), rel)
+            for name, g, e in zip(("rows", "offsets", "entries"), got, exp):
+                if g.shape != e.shape or not np.array_equal(g, e):
+                    bad.append((int(k), rel, name))
+                    break
+    ctx.release(tk)
+    assert not bad, "blocks differ from the oracle: %s" % bad[:10]
+
+
+SMALL = {
+    "cube": meshgen.cube(),
+    "cube_z": meshgen.cube([0, 0, 0, 0, 1, 1, 1, 1]),
+    "fig1": meshgen.fig1_toy(),
+    "fig4": meshgen.fig4_example(),
+    "single": meshgen.single_tet(),
+    "rand0": meshgen.random_small(0, n=4, nclusters=3),
+    "rand1": meshgen.random_small(1, n=5, nclusters=6, drop=0.5, isolated=4, empty_clusters=3),
+    "rand2": meshgen.random_small(2, n=6, nclusters=9, drop=0.2),
+    "grid6": meshgen.grid_mesh(6, 30, seed=4),
+}
+
+
+@pytest.mark.parametrize("form", ["plain", "batched"])
+@pytest.mark.parametrize("name", sorted(SMALL))
+def test_small_cases(name, form):
+    gale = _gale()
+    m = SMALL[name]
+    _say("case", name, form)
+    orc = oracle.Oracle.of(m)
+    with gale.Context(form=form) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        compare_all(ctx, m, orc)
+        for mask in (1, 2, 4, 3, 5, 6):
+            compare_all(ctx, m, orc, mask=mask)
+
+
+@pytest.mark.parametrize("name", ["cube", "rand1", "rand2", "grid6"])
+def test_global_memory_path(name):
+    """A tiny LDS budget sends every cluster down the global-workspace path."""
+    gale = _gale()
+    m = SMALL[name]
+    _say("global path", name)
+    orc = oracle.Oracle.of(m)
+    with gale.Context(form="batched", lds_bytes=256) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        compare_all(ctx, m, orc)
+        st = ctx.stats()
+        assert st["global_path_blocks"] > 0
+
+
+def test_one_cluster_per_vertex_and_whole_mesh():
+    gale = _gale()
+    base = meshgen.grid_mesh(5, 125, seed=9)
+    per_vertex = meshgen.Mesh(tets=base.tets, cluster=np.arange(base.nv, dtype=np.int32), nclusters=base.nv)
+    whole = meshgen.Mesh(tets=base.tets, cluster=np.zeros(base.nv, np.int32), nclusters=1)
+    for m in (per_vertex, whole):
+        _say("special clustering", m.nclusters)
+        orc = oracle.Oracle.of(m)
+        for form in ("plain", "batched"):
+            with gale.Context(form=form) as ctx:
+                ctx.load(m.tets, m.cluster, m.nclusters)
+                compare_all(ctx, m, orc)
+
+
+def test_config1_full():
+    gale = _gale()
+    m = meshgen.config(1)
+    _say("config 1 full")
+    orc = oracle.Oracle.of(m)
+    for form in ("plain", "batched"):
+        with gale.Context(form=form) as ctx:
+            ctx.load(m.tets, m.cluster, m.nclusters)
+            compare_all(ctx, m, orc)
+            st = ctx.stats()
+            assert st["entries_built"] == 714984 + 434558 + 703452
+
+
+def test_config1_as_one_cluster_global_path():
+    """178,746 tetrahedra in one cluster: too large for LDS, global path."""
+    gale = _gale()
+    base = meshgen.config(1)
+    m = meshgen.Mesh(tets=base.tets, cluster=np.zeros(base.nv, np.int32), nclusters=1)
+    _say("config 1 as one cluster")
+    orc = oracle.Oracle.of(m)
+    with gale.Context(form="batched") as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        compare_all(ctx, m, orc)
+
+
+def test_config2_sampled_and_totals():
+    """128^3 lattice, 2048 clusters, built in one batched launch (the
+    benchmark's configuration): a seeded sample of clusters plus the largest
+    ones compared with the oracle; every block checked against the closed
+    forms through the sums."""
+    gale = _gale()
+    m = meshgen.config(2)
+    _say("config 2")
+    with gale.Context(form="batched") as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        ids = np.arange(m.nclusters, dtype=np.int32)
+        tk = ctx.submit(ids, 7)
+        st = ctx.stats()
+        cf = pinlib.kuhn_counts(128)
+        assert st["entries_built"] == 4 * m.nt + 2 * cf["E"] + (4 * m.nt - cf["Fb"])
+        rng = np.random.default_rng(123)
+        sample = sorted(set(rng.choice(m.nclusters, 48, replace=False).tolist()) | {0, m.nclusters - 1})
+        orc = oracle.Oracle.of(m)
+        bad = []
+        tt_rows = 0
+        for k in range(m.nclusters):
+            rows, offs, ents = ctx.block(tk, k, 4)
+            tt_rows += len(rows)
+            if k in sample:
+                for rel in REL:
+                    got = ctx.block(tk, k, rel)
+                    exp = orc.block(k, rel)
+                    if not all(np.array_equal(g, e) for g, e in zip(got, exp)):
+                        bad.append((k, rel))
+        assert tt_rows == m.nt
+        ctx.release(tk)
+        assert not bad, bad
+
+
+def test_alone_equals_batched_and_repeatable():
+    """A block is the same byte string alone, in a batch, in either form, and
+    across repeated runs."""
+    gale = _gale()
+    m = meshgen.grid_mesh(12, 100, seed=5)
+    with gale.Context(form="batched") as a, gale.Context(form="plain") as b:
+        a.load(m.tets, m.cluster, m.nclusters)
+        b.load(m.tets, m.cluster, m.nclusters)
+        ids = np.arange(m.nclusters, dtype=np.int32)
+        t_all = a.submit(ids, 7)
+        t_all2 = a.submit(ids[::-1].copy(), 7)
+        for k in (0, 3, m.nclusters - 1):
+            t1 = b.submit([k], 7)
+            t2 = a.submit([k], 2)
+            for rel in REL:
+                x = a.block(t_all, k, rel)
+                y = b.block(t1, k, rel)
+                z = a.block(t_all2, k, rel)
+                assert all(np.array_equal(p, q) for p, q in zip(x, y))
+                assert all(np.array_equal(p, q) for p, q in zip(x, z))
+            x = a.block(t_all, k, 2)
+            y = a.block(t2, k, 2)
+            assert all(np.array_equal(p, q) for p, q in zip(x, y))
+            b.release(t1)
+            a.release(t2)
+        a.release(t_all)
+        a.release(t_all2)
+
+
+def test_error_paths():
+    gale = _gale()
+    m = SMALL["grid6"]
+    with gale.Context() as ctx:
+        with pytest.raises(gale.GaleError) as ei:
+            ctx.submit([0], 7)
+        assert ei.value.status == gale.ESTATE
+        bad = m.tets.copy()
+        bad[3, 1] = bad[3, 0]
+        with pytest.raises(gale.GaleError) as ei:
+            ctx.load(bad, m.cluster, m.nclusters)
+        assert ei.value.status == gale.EINVAL
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        for ids, mask in (([m.nclusters], 7), ([-1], 7), ([0], 0), ([0], 8)):
+            with pytest.raises(gale.GaleError) as ei:
+                ctx.submit(ids, mask)
+            assert ei.value.status == gale.EINVAL
+        tk = ctx.submit([0, 1], 1)
+        with pytest.raises(gale.GaleError) as ei:
+            ctx.block(tk, 0, 2)
+        assert ei.value.status == gale.ENOENT
+        with pytest.raises(gale.GaleError) as ei:
+            ctx.block(tk, 2, 1)
+        assert ei.value.status == gale.ENOENT
+        ctx.release(tk)
+        with pytest.raises(gale.GaleError) as ei:
+            ctx.release(tk)
+        assert ei.value.status == gale.ENOENT
+        with pytest.raises(gale.GaleError) as ei:
+            ctx.load(m.tets, m.cluster, m.nclusters)
+        assert ei.value.status == gale.ESTATE
