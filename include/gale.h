@@ -68,7 +68,7 @@ typedef struct {
     int32_t  device;              /* HIP device ordinal */
     int32_t  mode;                /* GALE_MODE_DIRECT or GALE_MODE_SERVE */
     int32_t  form;                /* DIRECT mode: GALE_FORM_PLAIN or GALE_FORM_BATCHED */
-    int32_t  block_threads;       /* threads per workgroup, 256 or 512; 0 = tuned default */
+    int32_t  block_threads;       /* threads per workgroup, 256, 512 or 1024; 0 = tuned default */
     int32_t  lds_bytes;           /* LDS budget per workgroup in bytes; 0 = tuned default; small values force the
                                      global-memory path (used by tests) */
     int32_t  max_inflight;        /* SERVE: batches on the GPU at once (1..8); 0 = 2 */
@@ -107,6 +107,8 @@ typedef struct {
     uint64_t kernel_launches;
     uint64_t overflow_reruns;       /* blocks rebuilt because a capacity bound was exceeded */
     uint64_t global_path_blocks;    /* blocks whose working set did not fit LDS */
+    uint64_t tt_exhaustive_blocks;  /* blocks whose TT face table could not pair every face (non-manifold face or
+                                       full table) and whose TT rows were built by exhaustive pairing */
     /* serving */
     uint64_t cache_hits, cache_misses, evictions;
     uint64_t cache_bytes_resident, cache_budget;

@@ -216,6 +216,7 @@ gale_status finalize_batch(gale_ctx *ctx, Batch &b, hipStream_t st) {
             return fail(GALE_EDEVICE, "stream metadata of cluster " + std::to_string(b.items[i].cluster) +
                                           " disagrees with the kernel's counts");
         if (h[0] & (kStVVOverflow | kStTTOverflow)) redo.push_back(i);
+        if (h[0] & kStTTFallback) ctx->n_tt_exhaustive++;
     }
     if (!redo.empty()) {
         Batch r;
@@ -480,8 +481,8 @@ gale_status gale_create(const gale_config *cfg_in, gale_ctx **out) {
     if (cfg_in) cfg = *cfg_in;
     if (cfg.mode != GALE_MODE_DIRECT && cfg.mode != GALE_MODE_SERVE) return fail(GALE_EINVAL, "unknown mode");
     if (cfg.form != GALE_FORM_PLAIN && cfg.form != GALE_FORM_BATCHED) return fail(GALE_EINVAL, "unknown form");
-    if (cfg.block_threads != 0 && cfg.block_threads != 256 && cfg.block_threads != 512)
-        return fail(GALE_EINVAL, "block_threads must be 256 or 512");
+    if (cfg.block_threads != 0 && cfg.block_threads != 256 && cfg.block_threads != 512 && cfg.block_threads != 1024)
+        return fail(GALE_EINVAL, "block_threads must be 256, 512 or 1024");
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || ndev <= 0) return fail(GALE_EDEVICE, "no HIP device");
@@ -499,7 +500,7 @@ gale_status gale_create(const gale_config *cfg_in, gale_ctx **out) {
         return fail(GALE_EDEVICE, std::string("device properties: ") + hipGetErrorString(e));
     }
     ctx->num_cus = prop.multiProcessorCount;
-    ctx->block_threads = cfg.block_threads ? cfg.block_threads : 256;
+    ctx->block_threads = cfg.block_threads ? cfg.block_threads : 1024;
     // LDS: the device limit minus what the kernels declare statically
     const int64_t static_lds = 512;
     int64_t budget = (int64_t)prop.sharedMemPerBlock - static_lds;
@@ -673,6 +674,7 @@ gale_status gale_get_stats(gale_ctx *ctx, gale_stats *out) {
     out->kernel_launches = ctx->n_launches;
     out->overflow_reruns = ctx->n_overflow;
     out->global_path_blocks = ctx->n_global_blocks;
+    out->tt_exhaustive_blocks = ctx->n_tt_exhaustive;
     out->entries_delivered = ctx->n_delivered;
     out->bytes_d2h = ctx->n_bytes_d2h;
     if (ctx->cfg.mode == GALE_MODE_SERVE) serve_stats(ctx, out);

@@ -152,7 +152,7 @@ struct gale_ctx {
     uint64_t next_ticket = 0;
     // counters
     std::atomic<uint64_t> n_requests{0}, n_blocks{0}, n_entries{0}, n_launches{0}, n_overflow{0},
-        n_global_blocks{0}, n_delivered{0}, n_bytes_d2h{0};
+        n_global_blocks{0}, n_delivered{0}, n_bytes_d2h{0}, n_tt_exhaustive{0};
     gale::Serve serve;
 };
 

@@ -40,6 +40,23 @@ namespace gale {
 
 constexpr int32_t kIdMask = 0x7fffffff;
 
+#ifdef GALE_PHASE_TIMING
+__device__ unsigned long long g_phase_cycles[32];
+#define PHASE_MARK(k)                                                              \
+    do {                                                                           \
+        __syncthreads();                                                           \
+        if (threadIdx.x == 0) {                                                    \
+            const unsigned long long now = __builtin_amdgcn_s_memtime();          \
+            atomicAdd(&g_phase_cycles[(k)], now - phase_t0);                       \
+            phase_t0 = now;                                                        \
+        }                                                                          \
+    } while (0)
+#else
+#define PHASE_MARK(k) \
+    do {              \
+    } while (0)
+#endif
+
 // ---------------------------------------------------------------------------
 // workgroup exclusive scan (wave64 shuffles + one LDS word per wave)
 // ---------------------------------------------------------------------------
@@ -152,6 +169,9 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
     unsigned long long *ib = reinterpret_cast<unsigned long long *>(smem + pl.ibits);
 
     if (tid == 0) s_status = 0;
+#ifdef GALE_PHASE_TIMING
+    unsigned long long phase_t0 = __builtin_amdgcn_s_memtime();
+#endif
 
     auto tet = [&](int p) -> int4 {
         if constexpr (kL) {
@@ -188,7 +208,23 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
         }
     }
     __syncthreads();
+    PHASE_MARK(0);
 
+#ifdef GALE_DEBUG_CHECKS
+    auto check_lt = [&](int bit) {
+        if constexpr (kL) {
+            for (int p = tid; p < ntot; p += B) {
+                int4 t = tg[p];
+                ushort4 q = lt[p];
+                if (q.x != (unsigned short)t.x || q.y != (unsigned short)t.y || q.z != (unsigned short)t.z ||
+                    q.w != (unsigned short)t.w)
+                    atomicOr(&s_status, bit);
+            }
+        }
+        __syncthreads();
+    };
+    check_lt(1 << 16);
+#endif
     // ---- VT / VV ---------------------------------------------------------
     if (mask & (kRelVT | kRelVV)) {
         RowT *rowOf = reinterpret_cast<RowT *>(base + pl.rowof);
@@ -214,6 +250,7 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
         if (tid == 0 && carry != nV) s_status |= kStInconsistent;
         for (int r = tid; r <= nV; r += B) cnt[r] = 0;
         __syncthreads();
+        PHASE_MARK(1);
 
         // count
         for (int p = tid; p < ns; p += B) {
@@ -226,6 +263,7 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
         }
         __syncthreads();
 
+        PHASE_MARK(2);
         // inclusive scan: cnt[r] = end of row r
         carry = 0;
         for (int r0 = 0; r0 < nV; r0 += B) {
@@ -244,6 +282,7 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
         }
         __syncthreads();
 
+        PHASE_MARK(3);
         // scatter stream positions; afterwards cnt[r] = start of row r
         if (vt_ok) {
             for (int p = tid; p < ns; p += B) {
@@ -257,6 +296,7 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
         }
         __syncthreads();
 
+        PHASE_MARK(4);
         if (vt_ok) {
             // sort each row's positions (rows are short; insertion sort)
             for (int r = tid; r < nV; r += B) {
@@ -274,11 +314,13 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
         }
         __syncthreads();
 
+        PHASE_MARK(5);
         if ((mask & kRelVT) && vt_ok) {
             for (int r = tid; r <= nV; r += B) blk[lay.vt_off + r] = cnt[r];
             for (int e = tid; e < nnz; e += B) blk[lay.vt_ent + e] = idg[lst[e]] & kIdMask;
         }
 
+        PHASE_MARK(6);
         if ((mask & kRelVV) && vt_ok) {
             uint32_t *bm = reinterpret_cast<uint32_t *>(base + pl.bm);
             const int rc = pl.rc, W = pl.W, Wp = pl.Wp;
@@ -329,8 +371,12 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
             }
         }
         __syncthreads();
+        PHASE_MARK(7);
     }
 
+#ifdef GALE_DEBUG_CHECKS
+    check_lt(1 << 17);
+#endif
     // ---- TT --------------------------------------------------------------
     if (mask & kRelTT) {
         SlotT *ht = reinterpret_cast<SlotT *>(base + pl.ht);
@@ -385,6 +431,7 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
         }
         __syncthreads();
 
+        PHASE_MARK(8);
         // faces of the other stream tetrahedra: attach where an internal face matches
         if (H > 0) {
             for (int p = tid; p < ntot; p += B) {
@@ -407,6 +454,10 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
             }
         }
         __syncthreads();
+#ifdef GALE_DEBUG_CHECKS
+        check_lt(1 << 18);
+#endif
+        PHASE_MARK(9);
         const bool fallback = s_fail != 0;
         if (tid == 0 && fallback) s_status |= kStTTFallback;
 
@@ -499,6 +550,7 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
             if (rcarry != nT) s_status |= kStInconsistent;
             if (ecarry > cap) s_status |= kStTTOverflow;
         }
+        PHASE_MARK(10);
     }
     __syncthreads();
 
@@ -513,6 +565,10 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
         h[5] = (mask & kRelTT) ? blk[5] : 0;
         h[6] = it.cap_vv;
         h[7] = it.cap_tt;
+#ifdef GALE_DEBUG_CHECKS
+        h[6] = (int32_t)pl.ht | (kL ? (1 << 30) : 0);
+        h[7] = (int32_t)pl.rowof;
+#endif
         for (int i = 0; i < 8; ++i) blk[i] = h[i];
         if (a.hdr)
             for (int i = 0; i < 8; ++i) a.hdr[(int64_t)it.hdr_index * 8 + i] = h[i];
@@ -572,7 +628,9 @@ __global__ __launch_bounds__(B) void gale_persistent_kernel(KArgs a) {
 // host-side launch wrappers
 // ---------------------------------------------------------------------------
 hipError_t launch_items(const KArgs &a, int block_threads, int grid, size_t lds, hipStream_t st) {
-    if (block_threads == 512) {
+    if (block_threads == 1024) {
+        hipLaunchKernelGGL(gale_items_kernel<1024>, dim3(grid), dim3(1024), lds, st, a);
+    } else if (block_threads == 512) {
         hipLaunchKernelGGL(gale_items_kernel<512>, dim3(grid), dim3(512), lds, st, a);
     } else {
         hipLaunchKernelGGL(gale_items_kernel<256>, dim3(grid), dim3(256), lds, st, a);
@@ -581,7 +639,9 @@ hipError_t launch_items(const KArgs &a, int block_threads, int grid, size_t lds,
 }
 
 hipError_t launch_persistent(const KArgs &a, int block_threads, int grid, size_t lds, hipStream_t st) {
-    if (block_threads == 512) {
+    if (block_threads == 1024) {
+        hipLaunchKernelGGL(gale_persistent_kernel<1024>, dim3(grid), dim3(1024), lds, st, a);
+    } else if (block_threads == 512) {
         hipLaunchKernelGGL(gale_persistent_kernel<512>, dim3(grid), dim3(512), lds, st, a);
     } else {
         hipLaunchKernelGGL(gale_persistent_kernel<256>, dim3(grid), dim3(256), lds, st, a);
@@ -597,10 +657,27 @@ hipError_t set_lds_limits(size_t lds) {
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)gale_persistent_kernel<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)gale_items_kernel<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)gale_persistent_kernel<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void *)gale_persistent_kernel<512>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
+#ifdef GALE_PHASE_TIMING
+extern "C" int gale_debug_phase_cycles(unsigned long long *out, int reset) {
+    hipError_t e = hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase_cycles), sizeof(g_phase_cycles));
+    if (reset) {
+        unsigned long long z[32] = {0};
+        hipMemcpyToSymbol(HIP_SYMBOL(g_phase_cycles), z, sizeof(z));
+    }
+    return (int)e;
+}
+#endif
+
 hipError_t persistent_occupancy(int block_threads, size_t lds, int *blocks_per_cu) {
+    if (block_threads == 1024)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<1024>, 1024, lds);
     if (block_threads == 512)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<512>, 512, lds);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<256>, 256, lds);

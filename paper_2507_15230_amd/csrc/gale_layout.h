@@ -147,48 +147,52 @@ GALE_HD int64_t align16(int64_t b) { return (b + 15) / 16 * 16; }
 
 // LDS path: tetrahedra staged as 4 x uint16 local ids (8 B), internal flags as
 // bits, rowOf int16, list positions uint16, face table slots 2 x uint16.
+// Every field is assigned on every path and ok is decided last (no early
+// return), so all callers see the same offsets whatever the mask.
 GALE_HD Plan lds_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32_t block_threads) {
     Plan p{};
-    p.ok = 0;
     const int64_t ntot = (int64_t)m.ns + m.nh;
-    if (m.L > 65535 || m.nV > 32767 || ntot > 16383) return p;
+    const bool narrow = m.L <= 65535 && m.nV <= 32767 && ntot <= 16383;
+    const bool want_tt = (mask & kRelTT) != 0;
+    const bool want_v = (mask & (kRelVT | kRelVV)) != 0;
+    const bool want_vv = (mask & kRelVV) != 0;
     p.W = (m.L + 31) / 32;
     p.Wp = p.W | 1;
-    p.H = (mask & kRelTT) ? face_table_slots(m.nT) : 0;
+    p.H = want_tt ? face_table_slots(m.nT) : 0;
     p.tets = 0;
-    int64_t off = align16(ntot * 8);
-    p.ibits = off;
-    if (mask & kRelTT) off = align16(off + (int64_t)((m.ns + 63) / 64) * 8);
-    const int64_t region = off;
-    int64_t bytesB = (mask & kRelTT) ? align16((int64_t)p.H * 4) : 0;
-    int64_t bytesA = 0;
+    p.ibits = align16(ntot * 8);
+    const int64_t region = p.ibits + (want_tt ? align16((int64_t)((m.ns + 63) / 64) * 8) : 0);
+    const int64_t bytesB = want_tt ? align16((int64_t)p.H * 4) : 0;
+    const int64_t a_rowof = 0;
+    const int64_t a_cnt = a_rowof + align16((int64_t)m.L * 2);
+    const int64_t a_lst = a_cnt + align16(((int64_t)m.nV + 1) * 4);
+    const int64_t a_bm = a_lst + align16((int64_t)m.nnzVT * 2);
+    p.rowof = region + a_rowof;
+    p.cnt = region + a_cnt;
+    p.lst = region + a_lst;
+    p.bm = region + a_bm;
+    p.ht = region;
+    // VV rows per bitmap pass: the largest of min(nV, block), halved down to
+    // 16, whose bitmap fits next to the lists
     int32_t rc = 0;
-    if (mask & (kRelVT | kRelVV)) {
-        p.rowof = region;
-        int64_t a = align16((int64_t)m.L * 2);
-        p.cnt = region + a;
-        a += align16(((int64_t)m.nV + 1) * 4);
-        p.lst = region + a;
-        a += align16((int64_t)m.nnzVT * 2);
-        p.bm = region + a;
-        if (mask & kRelVV) {
-            rc = m.nV < block_threads ? m.nV : block_threads;
-            while (rc > 0) {
-                int64_t need = region + a + align16((int64_t)rc * p.Wp * 4);
-                int64_t need2 = region + bytesB;
-                if ((need > need2 ? need : need2) <= budget) break;
-                if (rc <= 16) { rc = -1; break; }
-                rc = rc / 2;
+    bool rc_ok = true;
+    if (want_vv) {
+        rc = m.nV < block_threads ? m.nV : block_threads;
+        rc_ok = rc == 0;
+        while (rc > 0) {
+            const int64_t need = region + a_bm + align16((int64_t)rc * p.Wp * 4);
+            if (need <= budget) {
+                rc_ok = true;
+                break;
             }
-            if (rc < 0) return p;
-            a += align16((int64_t)rc * p.Wp * 4);
+            if (rc <= 16) break;
+            rc = rc / 2;
         }
-        bytesA = a;
     }
     p.rc = rc;
-    p.ht = region;
+    const int64_t bytesA = want_v ? a_bm + (want_vv ? align16((int64_t)rc * p.Wp * 4) : 0) : 0;
     p.bytes = region + (bytesA > bytesB ? bytesA : bytesB);
-    p.ok = p.bytes <= budget ? 1 : 0;
+    p.ok = (narrow && rc_ok && p.bytes <= budget) ? 1 : 0;
     return p;
 }
 

@@ -224,6 +224,7 @@ void complete_slot(gale_ctx *ctx, Slot &sl, std::vector<int64_t> &rebuild) {
             continue;
         }
         std::memcpy(e.hdr, h, sizeof(e.hdr));
+        if (h[0] & kStTTFallback) ctx->n_tt_exhaustive++;
         e.state = 1;
         if (e.pins == 0 && !e.in_lru) {
             s.lru.push_back(sl.keys[i]);

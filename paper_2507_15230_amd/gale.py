@@ -44,6 +44,7 @@ class GaleStats(C.Structure):
         ("device_mesh_bytes", C.c_uint64), ("load_seconds", C.c_double),
         ("requests", C.c_uint64), ("blocks_built", C.c_uint64), ("entries_built", C.c_uint64),
         ("kernel_launches", C.c_uint64), ("overflow_reruns", C.c_uint64), ("global_path_blocks", C.c_uint64),
+        ("tt_exhaustive_blocks", C.c_uint64),
         ("cache_hits", C.c_uint64), ("cache_misses", C.c_uint64), ("evictions", C.c_uint64),
         ("cache_bytes_resident", C.c_uint64), ("cache_budget", C.c_uint64),
         ("entries_delivered", C.c_uint64), ("bytes_d2h", C.c_uint64), ("batches", C.c_uint64),
