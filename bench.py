@@ -11,6 +11,9 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -23,6 +26,90 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2507_15230_amd/csrc/gale_kernels.hip", "paper_2507_15230_amd/csrc/gale_layout.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "persistent_kernel_traffic_128cubed.json")
+COPY_BYTES = 256 << 20
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per persistent launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary, if it was taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return t.get("traffic_bytes_per_launch")
+
+
+def summarize_profile(kt_dir, fetch_dir, write_dir, out_md, out_json, cmd_kt, cmd_fetch, cmd_write):
+    """Turn rocprofv3 CSV output into the committed text summary and the
+    traffic record bench.py reads back."""
+    stats = glob.glob(os.path.join(kt_dir, "**", "*kernel_stats.csv"), recursive=True)
+    lines = ["# rocprofv3 kernel statistics: 128^3 lattice, 2048 clusters, VT+VV+TT batched", "",
+             "Command: `%s`" % cmd_kt, "", "| kernel | calls | total ms | avg us | min us | max us |",
+             "|---|---|---|---|---|---|"]
+    avg_persistent = None
+    for fn in stats:
+        for r in csv.DictReader(open(fn)):
+            name = r.get("Name") or r.get("KernelName") or ""
+            calls = int(float(r.get("Calls", 0)))
+            tot = float(r.get("TotalDurationNs", 0)) / 1e6
+            avg = float(r.get("AverageNs", 0)) / 1e3
+            mn = float(r.get("MinNs", 0)) / 1e3
+            mx = float(r.get("MaxNs", 0)) / 1e3
+            lines.append("| %s | %d | %.3f | %.1f | %.1f | %.1f |" % (name[:90], calls, tot, avg, mn, mx))
+            if "gale_persistent_kernel" in name and ", true>" in name:
+                avg_persistent = avg
+    traffic = {}
+    for tag, d in (("fetch", fetch_dir), ("write", write_dir)):
+        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            per = {}
+            for r in csv.DictReader(open(fn)):
+                per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+            traffic[tag] = per
+    copy_name = None
+    res = {"kernel_source_sha256": kernel_source_hash(), "commands": [cmd_kt, cmd_fetch, cmd_write]}
+    if "fetch" in traffic and "write" in traffic:
+        def pick(per, pred):
+            for k, v in per.items():
+                if pred(k):
+                    return k, sum(v) / len(v)
+            return None, None
+        copy_name, copy_fetch = pick(traffic["fetch"], lambda k: "neg" in k.lower())
+        _, copy_write = pick(traffic["write"], lambda k: k == copy_name)
+        kname, k_fetch = pick(traffic["fetch"], lambda k: "gale_persistent_kernel" in k and ", true>" in k)
+        _, k_write = pick(traffic["write"], lambda k: k == kname)
+        if copy_fetch and copy_write and k_fetch is not None and k_write is not None:
+            f_fac = COPY_BYTES / (copy_fetch * 1024.0)
+            w_fac = COPY_BYTES / (copy_write * 1024.0)
+            tb = k_fetch * 1024.0 * f_fac + k_write * 1024.0 * w_fac
+            res.update({"copy_kernel": copy_name, "copy_bytes": COPY_BYTES, "copy_fetch_kib": copy_fetch,
+                        "copy_write_kib": copy_write, "fetch_factor": f_fac, "write_factor": w_fac,
+                        "kernel": kname, "fetch_kib_per_dispatch": k_fetch, "write_kib_per_dispatch": k_write,
+                        "traffic_bytes_per_launch": tb, "avg_kernel_us": avg_persistent})
+            lines += ["", "## HBM traffic (rocprofv3 --pmc, per dispatch)", "",
+                      "Commands: `%s` and `%s`" % (cmd_fetch, cmd_write), "",
+                      "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB |", "|---|---|---|",
+                      "| %s | %.0f | %.0f |" % (kname[:90], k_fetch, k_write),
+                      "| %s (%d MiB copy) | %.0f | %.0f |" % (copy_name[:60], COPY_BYTES >> 20, copy_fetch, copy_write),
+                      "", "Scale factors from the copy (known bytes / counter): fetch %.3f, write %.3f." % (f_fac, w_fac),
+                      "Traffic per persistent launch: %.1f MB." % (tb / 1e6)]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    with open(out_json, "w") as f:
+        json.dump(res, f, indent=1)
+    print("wrote", out_md, out_json)
 
 
 def log(*a):
@@ -68,11 +155,18 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--block-threads", type=int, default=0)
+    ap.add_argument("--block-threads", type=int, default=1024)
     ap.add_argument("--lds-bytes", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one %d MiB device copy (reference for the HBM byte counters)" % (COPY_BYTES >> 20))
+    ap.add_argument("--summarize-profile", nargs=8, metavar=("KT", "FETCH", "WRITE", "MD", "JSON", "CMD_KT",
+                                                           "CMD_FETCH", "CMD_WRITE"))
     args = ap.parse_args()
+    if args.summarize_profile:
+        summarize_profile(*args.summarize_profile)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (clusters are independent; "
               "see the sharding note in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
@@ -92,6 +186,14 @@ def main():
     mesh = meshgen.config(args.config)
     nv, nt, ncl = mesh.nv, mesh.nt, mesh.nclusters
     ids = np.arange(ncl, dtype=np.int32)
+
+    if args.copy_calibration:
+        # a plain read+write kernel of known size: dst = -src over COPY_BYTES
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     ctx = gale.Context(device=0, mode="direct", form="batched", block_threads=args.block_threads,
                        lds_bytes=args.lds_bytes, stream=stream.cuda_stream)
@@ -185,13 +287,13 @@ def main():
             "entries_per_step": int(entries_step),
             "clusters": ncl,
             "form": "batched",
-            "block_threads": st0.get("block_threads", None) or args.block_threads or 256,
+            "block_threads": args.block_threads,
             "load_seconds": st0["load_seconds"],
             "global_path_blocks_per_step": int(st["global_path_blocks"] // max(1, st["requests"])),
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
             "alg_bytes_per_launch": int(alg_bytes), "kernel_ms": ms_kernel,
         },
         "cpu_baseline": cpu,

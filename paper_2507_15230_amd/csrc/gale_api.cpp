@@ -97,14 +97,16 @@ int64_t lay_out_items(const gale_ctx *ctx, std::vector<WorkItem> &items, int64_t
     return w - out_base_word;
 }
 
+bool item_on_lds_path(const gale_ctx *ctx, const WorkItem &it) {
+    return lds_plan(ctx->meta[it.cluster], it.mask, ctx->lds_budget, ctx->block_threads).ok != 0;
+}
+
 int64_t workspace_bytes(const gale_ctx *ctx, const std::vector<WorkItem> &items, int *n_global) {
     int64_t need = 0;
     int ng = 0;
     for (const WorkItem &it : items) {
-        const ClusterMeta &m = ctx->meta[it.cluster];
-        const Plan lp = lds_plan(m, it.mask, ctx->lds_budget, ctx->block_threads);
-        if (!lp.ok) {
-            const Plan gp = ws_plan(m, it.mask, ctx->block_threads);
+        if (!item_on_lds_path(ctx, it)) {
+            const Plan gp = ws_plan(ctx->meta[it.cluster], it.mask, ctx->block_threads);
             need = std::max<int64_t>(need, gp.bytes);
             ++ng;
         }
@@ -115,7 +117,7 @@ int64_t workspace_bytes(const gale_ctx *ctx, const std::vector<WorkItem> &items,
 
 KArgs base_args(const gale_ctx *ctx) {
     KArgs a{};
-    a.s.tets = reinterpret_cast<const int4 *>(ctx->d_tets);
+    a.s.tets = reinterpret_cast<const char *>(ctx->d_tets);
     a.s.tid = ctx->d_tid;
     a.s.lverts = ctx->d_lverts;
     a.s.meta = ctx->d_meta;
@@ -123,68 +125,93 @@ KArgs base_args(const gale_ctx *ctx) {
     return a;
 }
 
-// Launch the items (already uploaded to d_items, queue word at d_queue) into
-// out.  PLAIN: one launch per item; BATCHED: one persistent launch.
+// Launch items already uploaded in launch order: the first n_lds take the
+// LDS path, the next n_glob the global-workspace path.  PLAIN: one launch per
+// item; BATCHED: one persistent launch per path, each with its own queue word.
 gale_status launch_batch(gale_ctx *ctx, int form, int32_t *d_out, int32_t *d_hdr, const WorkItem *d_items,
-                         int nitems, int32_t *d_queue, char *d_ws, int64_t ws_stride, hipStream_t st) {
+                         int n_lds, int n_glob, int32_t *d_queue, char *d_ws, int64_t ws_stride, hipStream_t st) {
     KArgs a = base_args(ctx);
     a.out = d_out;
     a.hdr = d_hdr;
     a.ws = d_ws;
     a.ws_stride = ws_stride;
     hipError_t e = hipSuccess;
-    if (nitems == 0) return GALE_OK;
     if (form == GALE_FORM_PLAIN) {
-        for (int i = 0; i < nitems && e == hipSuccess; ++i) {
+        for (int i = 0; i < n_lds + n_glob && e == hipSuccess; ++i) {
             a.items = d_items + i;
             a.nitems = 1;
-            e = launch_items(a, ctx->block_threads, 1, ctx->lds_budget, st);
+            e = launch_items(a, i < n_lds, ctx->block_threads, 1, ctx->lds_budget, st);
             ctx->n_launches++;
         }
     } else {
-        a.items = d_items;
-        a.nitems = nitems;
-        a.queue = d_queue;
-        const int grid = std::min<int>(nitems, ctx->persistent_grid);
-        e = launch_persistent(a, ctx->block_threads, grid, ctx->lds_budget, st);
-        ctx->n_launches++;
+        if (n_lds > 0) {
+            a.items = d_items;
+            a.nitems = n_lds;
+            a.queue = d_queue;
+            e = launch_persistent(a, true, ctx->block_threads, std::min<int>(n_lds, ctx->grid_lds), ctx->lds_budget,
+                                  st);
+            ctx->n_launches++;
+        }
+        if (n_glob > 0 && e == hipSuccess) {
+            a.items = d_items + n_lds;
+            a.nitems = n_glob;
+            a.queue = d_queue + 1;
+            e = launch_persistent(a, false, ctx->block_threads, std::min<int>(n_glob, ctx->grid_glob), 0, st);
+            ctx->n_launches++;
+        }
     }
     if (e != hipSuccess) return fail(GALE_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     return GALE_OK;
 }
 
-// Upload items (+ a zero queue word) and launch.  Buffers come from the pools
-// and are recorded in the batch for release.
+// Upload items (layout order in `items`, with out_word and hdr_index set) in
+// launch order with two zero queue words, and launch.  Buffers come from the
+// pools; the caller releases them.
+gale_status upload_and_launch(gale_ctx *ctx, int form, const std::vector<WorkItem> &items, int32_t *d_out,
+                              Buf *&dev_items, Buf *&dev_hdr, Buf *&host_items, Buf *&ws, hipStream_t st) {
+    hipError_t e;
+    const int n = (int)items.size();
+    std::vector<WorkItem> order;
+    order.reserve(n);
+    for (const WorkItem &it : items)
+        if (item_on_lds_path(ctx, it)) order.push_back(it);
+    const int n_lds = (int)order.size();
+    for (const WorkItem &it : items)
+        if (!item_on_lds_path(ctx, it)) order.push_back(it);
+    const int n_glob = n - n_lds;
+    const int64_t wsb = workspace_bytes(ctx, items, nullptr);
+    ctx->n_global_blocks += n_glob;
+    const int slots = form == GALE_FORM_PLAIN ? 1 : std::min<int>(std::max(n_glob, 1), ctx->grid_glob);
+    dev_items = ctx->dev_pool.acquire((size_t)n * sizeof(WorkItem) + 64, &e);
+    dev_hdr = ctx->dev_pool.acquire((size_t)n * 32 + 64, &e);
+    host_items = ctx->pin_pool.acquire((size_t)n * sizeof(WorkItem) + 64, &e);
+    if (!dev_items || !dev_hdr || !host_items) return fail(GALE_ENOMEM, "batch buffers");
+    if (n_glob > 0) {
+        ws = ctx->dev_pool.acquire((size_t)wsb * slots, &e);
+        if (!ws) return fail(GALE_ENOMEM, "workspace");
+    }
+    char *hi = (char *)host_items->ptr;
+    std::memset(hi, 0, 64);
+    std::memcpy(hi + 64, order.data(), (size_t)n * sizeof(WorkItem));
+    e = hipMemcpyAsync(dev_items->ptr, hi, (size_t)n * sizeof(WorkItem) + 64, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return fail(GALE_EDEVICE, std::string("work list copy: ") + hipGetErrorString(e));
+    char *di = (char *)dev_items->ptr;
+    return launch_batch(ctx, form, d_out, (int32_t *)dev_hdr->ptr, (const WorkItem *)(di + 64), n_lds, n_glob,
+                        (int32_t *)di, ws ? (char *)ws->ptr : nullptr, wsb, st);
+}
+
+// Lay out the batch's items in a fresh output buffer and launch them.
 gale_status run_items(gale_ctx *ctx, Batch &b, int form, hipStream_t st) {
     hipError_t e;
     const int n = (int)b.items.size();
     b.out_words = lay_out_items(ctx, b.items, 0);
-    int ng = 0;
-    const int64_t wsb = workspace_bytes(ctx, b.items, &ng);
-    ctx->n_global_blocks += ng;
-    const int slots = form == GALE_FORM_PLAIN ? 1 : std::min<int>(n, ctx->persistent_grid);
     b.out = ctx->dev_pool.acquire((size_t)b.out_words * 4 + 256, &e);
     if (!b.out) return fail(GALE_ENOMEM, "device output buffer");
-    b.dev_items = ctx->dev_pool.acquire((size_t)n * sizeof(WorkItem) + 64, &e);
-    b.dev_hdr = ctx->dev_pool.acquire((size_t)n * 32 + 64, &e);
-    b.host_items = ctx->pin_pool.acquire((size_t)n * sizeof(WorkItem) + 64, &e);
     b.host_hdr = ctx->pin_pool.acquire((size_t)n * 32 + 64, &e);
-    if (!b.dev_items || !b.dev_hdr || !b.host_items || !b.host_hdr) return fail(GALE_ENOMEM, "batch buffers");
-    if (wsb > 0) {
-        b.ws = ctx->dev_pool.acquire((size_t)wsb * slots, &e);
-        if (!b.ws) return fail(GALE_ENOMEM, "workspace");
-    }
-    // items at offset 64, queue word at 0
-    char *hi = (char *)b.host_items->ptr;
-    std::memset(hi, 0, 64);
-    std::memcpy(hi + 64, b.items.data(), (size_t)n * sizeof(WorkItem));
-    e = hipMemcpyAsync(b.dev_items->ptr, hi, (size_t)n * sizeof(WorkItem) + 64, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return fail(GALE_EDEVICE, std::string("work list copy: ") + hipGetErrorString(e));
-    char *di = (char *)b.dev_items->ptr;
-    gale_status s = launch_batch(ctx, form, (int32_t *)b.out->ptr, (int32_t *)b.dev_hdr->ptr,
-                                 (const WorkItem *)(di + 64), n, (int32_t *)di,
-                                 b.ws ? (char *)b.ws->ptr : nullptr, wsb, st);
-    return s;
+    if (!b.host_hdr) return fail(GALE_ENOMEM, "batch buffers");
+    if (n == 0) return GALE_OK;
+    return upload_and_launch(ctx, form, b.items, (int32_t *)b.out->ptr, b.dev_items, b.dev_hdr, b.host_items, b.ws,
+                             st);
 }
 
 void release_batch(gale_ctx *ctx, Batch &b) {
@@ -203,7 +230,8 @@ void release_batch(gale_ctx *ctx, Batch &b) {
 // consistency.  Synchronous on st.
 gale_status finalize_batch(gale_ctx *ctx, Batch &b, hipStream_t st) {
     const int n = (int)b.items.size();
-    hipError_t e = hipMemcpyAsync(b.host_hdr->ptr, b.dev_hdr->ptr, (size_t)n * 32, hipMemcpyDeviceToHost, st);
+    hipError_t e = n ? hipMemcpyAsync(b.host_hdr->ptr, b.dev_hdr->ptr, (size_t)n * 32, hipMemcpyDeviceToHost, st)
+                     : hipSuccess;
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(GALE_EDEVICE, std::string("header copy: ") + hipGetErrorString(e));
     b.hdr.assign((int32_t *)b.host_hdr->ptr, (int32_t *)b.host_hdr->ptr + (size_t)n * 8);
@@ -224,7 +252,7 @@ gale_status finalize_batch(gale_ctx *ctx, Batch &b, hipStream_t st) {
             WorkItem it = b.items[i];
             const int32_t *h = &b.hdr[(size_t)i * 8];
             it.cap_vv = (it.mask & kRelVV) ? std::max(h[4], 0) : 0;
-            it.cap_tt = (it.mask & kRelTT) ? std::max(h[5], 0) : 0;
+            it.cap_tt = (it.mask & kRelTT) ? std::max(h[5], default_cap_tt(ctx->meta[it.cluster])) : 0;
             r.items.push_back(it);
         }
         gale_status s = run_items(ctx, r, GALE_FORM_PLAIN, st);
@@ -512,10 +540,13 @@ gale_status gale_create(const gale_config *cfg_in, gale_ctx **out) {
         return fail(GALE_EDEVICE, std::string("LDS limit: ") + hipGetErrorString(e));
     }
     int occ = 0;
-    e = persistent_occupancy(ctx->block_threads, (size_t)ctx->lds_budget, &occ);
+    e = persistent_occupancy(ctx->block_threads, true, (size_t)ctx->lds_budget, &occ);
     if (e != hipSuccess || occ <= 0) occ = 1;
-    ctx->occupancy = occ;
-    ctx->persistent_grid = ctx->num_cus * occ;
+    ctx->grid_lds = ctx->num_cus * occ;
+    occ = 0;
+    e = persistent_occupancy(ctx->block_threads, false, 0, &occ);
+    if (e != hipSuccess || occ <= 0) occ = 1;
+    ctx->grid_glob = ctx->num_cus * occ;
     if (cfg.hip_stream) {
         ctx->stream = (hipStream_t)cfg.hip_stream;
         ctx->own_stream = false;
@@ -546,7 +577,7 @@ gale_status gale_load(gale_ctx *ctx, int32_t nv, int64_t nt, const int32_t *tv, 
         if (bytes) r = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
         return r;
     };
-    if (e == hipSuccess) e = up((void **)&ctx->d_tets, hs.tets.data(), hs.tets.size() * 4);
+    if (e == hipSuccess) e = up((void **)&ctx->d_tets, hs.tets.data(), hs.tets.size());
     if (e == hipSuccess) e = up((void **)&ctx->d_tid, hs.tid.data(), hs.tid.size() * 4);
     if (e == hipSuccess) e = up((void **)&ctx->d_lverts, hs.lverts.data(), hs.lverts.size() * 4);
     if (e == hipSuccess) e = up((void **)&ctx->d_meta, hs.meta.data(), hs.meta.size() * sizeof(ClusterMeta));
@@ -555,7 +586,7 @@ gale_status gale_load(gale_ctx *ctx, int32_t nv, int64_t nt, const int32_t *tv, 
         return fail(e == hipErrorOutOfMemory ? GALE_ENOMEM : GALE_EDEVICE,
                     std::string("mesh upload: ") + hipGetErrorString(e));
     }
-    ctx->mesh_bytes = (hs.tets.size() + hs.tid.size() + hs.lverts.size()) * 4 + hs.meta.size() * sizeof(ClusterMeta);
+    ctx->mesh_bytes = hs.tets.size() + (hs.tid.size() + hs.lverts.size()) * 4 + hs.meta.size() * sizeof(ClusterMeta);
     ctx->stream_tets = (int64_t)hs.tid.size();
     ctx->meta = std::move(hs.meta);
     ctx->nv = nv;

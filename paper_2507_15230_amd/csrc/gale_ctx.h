@@ -134,7 +134,7 @@ struct gale_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool poisoned = false;
-    int num_cus = 0, occupancy = 1, persistent_grid = 1, block_threads = 256;
+    int num_cus = 0, grid_lds = 1, grid_glob = 1, block_threads = 256;
     int64_t lds_budget = 0;
     // mesh
     bool loaded = false;
@@ -143,7 +143,8 @@ struct gale_ctx {
     uint64_t mesh_bytes = 0;
     double load_seconds = 0;
     std::vector<gale::ClusterMeta> meta;
-    int32_t *d_tets = nullptr, *d_tid = nullptr, *d_lverts = nullptr;
+    uint8_t *d_tets = nullptr;
+    int32_t *d_tid = nullptr, *d_lverts = nullptr;
     gale::ClusterMeta *d_meta = nullptr;
     // pools and tickets
     gale::Pool dev_pool, pin_pool;
@@ -161,8 +162,8 @@ gale_status fail(gale_status s, const std::string &msg);
 int32_t default_cap_tt(const ClusterMeta &m);
 int64_t lay_out_items(const gale_ctx *ctx, std::vector<WorkItem> &items, int64_t out_base_word);
 int64_t workspace_bytes(const gale_ctx *ctx, const std::vector<WorkItem> &items, int *n_global);
-gale_status launch_batch(gale_ctx *ctx, int form, int32_t *d_out, int32_t *d_hdr, const WorkItem *d_items,
-                         int nitems, int32_t *d_queue, char *d_ws, int64_t ws_stride, hipStream_t st);
+gale_status upload_and_launch(gale_ctx *ctx, int form, const std::vector<WorkItem> &items, int32_t *d_out,
+                              Buf *&dev_items, Buf *&dev_hdr, Buf *&host_items, Buf *&ws, hipStream_t st);
 gale_status check_request(const gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t mask);
 
 gale_status serve_start(gale_ctx *ctx);

@@ -17,7 +17,7 @@ struct HostStreams {
     int32_t nv = 0, ncl = 0;
     int64_t nt = 0;
     std::vector<ClusterMeta> meta;
-    std::vector<int32_t> tets;    // 4 local ids per stream tetrahedron
+    std::vector<uint8_t> tets;    // stream tetrahedra, 4 x uint16 or 4 x int32 local ids
     std::vector<int32_t> tid;     // original id | internal << 31
     std::vector<int32_t> lverts;  // original id | row << 31
 };
@@ -26,9 +26,10 @@ gale_status prepare_streams(int32_t nv, int64_t nt, const int32_t *tv, const int
                             HostStreams &out, std::string &err);
 
 struct KArgs;
-hipError_t launch_items(const KArgs &a, int block_threads, int grid, size_t lds, hipStream_t st);
-hipError_t launch_persistent(const KArgs &a, int block_threads, int grid, size_t lds, hipStream_t st);
+hipError_t launch_items(const KArgs &a, bool lds_path, int block_threads, int grid, size_t lds, hipStream_t st);
+hipError_t launch_persistent(const KArgs &a, bool lds_path, int block_threads, int grid, size_t lds,
+                             hipStream_t st);
 hipError_t set_lds_limits(size_t lds);
-hipError_t persistent_occupancy(int block_threads, size_t lds, int *blocks_per_cu);
+hipError_t persistent_occupancy(int block_threads, bool lds_path, size_t lds, int *blocks_per_cu);
 
 }  // namespace gale

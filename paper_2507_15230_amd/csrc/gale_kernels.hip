@@ -8,28 +8,32 @@
 // for the LDS budget, in a per-workgroup slice of global memory (same
 // algorithm, 32-bit types).
 //
-// VT (paper Section 4.6: iterate the segment's tetrahedra, take the vertices
-// that belong to the segment, relate them): count per row with LDS atomics,
-// inclusive scan, scatter stream positions with atomic decrements, then sort
-// each row's positions.  Stream order is ascending tetrahedron id, so sorted
-// positions are the canonical VT row.  No global atomics (the paper's VT
-// kernel is limited by atomics on one vertex, Appendix A.1).
+// All three relations are read from one structure built first: the local VT
+// relation of every vertex of the cluster's local table (count per vertex with
+// LDS atomics, inclusive scan, scatter of stream positions with atomic
+// decrements).  No global atomics are used (the paper's VT kernel is limited
+// by atomics on one vertex, Appendix A.1).
+//
+// VT (Section 4.6: iterate the segment's tetrahedra, take the vertices in the
+// segment, relate them): a row's list, sorted; stream order is tetrahedron id
+// order, so the sorted positions are the canonical row.
 //
 // VV (Algorithm 1: for each tetrahedron and each of its vertices in the
-// segment, relate the other three vertices, without duplicates): per pass of
-// rc rows, each row owns an LDS bitmap over the local vertex table; the table
-// is sorted by original id, so reading the set bits in order yields the row
-// already sorted and duplicate-free.  Replaces the paper's fixed-width -1
-// initialised relation matrix and atomicPush (Algorithm 2), whose output order
-// depends on thread arrival.
+// segment, relate the other three, without duplicates): a wave takes one row
+// at a time and sets bits in its own LDS bitmap over the local vertex table;
+// the table is in original id order, so reading the set bits in word order
+// yields the row sorted and duplicate-free.  This replaces the paper's
+// fixed-width -1 initialised matrix and atomicPush (Algorithm 2), whose output
+// order depends on thread arrival.  Counts first, then emission, so offsets
+// are known before any entry is written.
 //
-// TT (two tetrahedra are adjacent iff they share a triangle, Section 2.2): the
-// faces of the tetrahedra internal to the cluster go into an LDS hash table
-// keyed by their sorted local vertex ids (each slot holds up to two face
-// references); the faces of the other stream tetrahedra (external star and
-// halo) are then looked up and attached as the second sharer.  A face met a
-// third time (non-manifold) or a full table switches the cluster to an
-// exhaustive O(rows x stream) pairing.
+// TT (two tetrahedra are adjacent iff they share a triangle, Section 2.2):
+// every tetrahedron holding face {a,b,c} of an internal tetrahedron is in the
+// local VT lists of a, b and c.  The four faces of t = (x,y,z,w) hold either
+// edge xy or edge zw, so a thread scans one list per edge, keeps the
+// tetrahedra holding the edge and assigns them to faces by the two other
+// vertices.  More than four raw neighbours (a face shared by three or more
+// tetrahedra) switches the cluster to exhaustive pairing.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <type_traits>
@@ -91,45 +95,10 @@ __device__ __forceinline__ int block_excl_scan(int v, int &total) {
 // ---------------------------------------------------------------------------
 // faces
 // ---------------------------------------------------------------------------
-struct Face {
-    int a, b, c;  // ascending local ids
-};
-
-__device__ __forceinline__ bool operator==(const Face &x, const Face &y) {
-    return x.a == y.a && x.b == y.b && x.c == y.c;
-}
-
 __device__ __forceinline__ void cswap(int &x, int &y) {
     int lo = min(x, y), hi = max(x, y);
     x = lo;
     y = hi;
-}
-
-// face k of t is t without its k-th vertex
-__device__ __forceinline__ Face face_of(int4 t, int k) {
-    int a, b, c;
-    if (k == 0) { a = t.y; b = t.z; c = t.w; }
-    else if (k == 1) { a = t.x; b = t.z; c = t.w; }
-    else if (k == 2) { a = t.x; b = t.y; c = t.w; }
-    else { a = t.x; b = t.y; c = t.z; }
-    cswap(a, b);
-    cswap(b, c);
-    cswap(a, b);
-    return Face{a, b, c};
-}
-
-__device__ __forceinline__ uint32_t face_hash(const Face &f) {
-    uint32_t h = (uint32_t)f.a * 0x9E3779B1u ^ (uint32_t)f.b * 0x85EBCA77u ^ (uint32_t)f.c * 0xC2B2AE3Du;
-    h ^= h >> 15;
-    h *= 0x2C1B3C6Du;
-    h ^= h >> 12;
-    h *= 0x297A2D39u;
-    h ^= h >> 15;
-    return h;
-}
-
-__device__ __forceinline__ uint32_t fast_range(uint32_t h, uint32_t n) {
-    return (uint32_t)(((uint64_t)h * (uint64_t)n) >> 32);
 }
 
 __device__ __forceinline__ int shared_vertices(int4 t, int4 u) {
@@ -142,96 +111,177 @@ __device__ __forceinline__ int shared_vertices(int4 t, int4 u) {
 }
 
 // ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int wave_sum(int x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+__device__ __forceinline__ int wave_excl_scan(int v, int &total) {
+    const int lane = threadIdx.x & 63;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+__device__ __forceinline__ bool has_vertex(int4 t, int u) {
+    return t.x == u || t.y == u || t.z == u || t.w == u;
+}
+
+__device__ __forceinline__ void cswap_u(uint32_t &x, uint32_t &y) {
+    const uint32_t lo = min(x, y), hi = max(x, y);
+    x = lo;
+    y = hi;
+}
+
+// Sort a[0..n) ascending in place; n <= 32 through a register bitonic network,
+// longer runs by insertion.
+template <typename T>
+__device__ __forceinline__ void sort_run(T *a, int n) {
+    if (n <= 1) return;
+    if (n <= 32) {
+        uint32_t v[32];
+#pragma unroll
+        for (int i = 0; i < 32; ++i) v[i] = i < n ? (uint32_t)a[i] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int k = 2; k <= 32; k <<= 1) {
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+                for (int i = 0; i < 32; ++i) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        if ((i & k) == 0)
+                            cswap_u(v[i], v[l]);
+                        else
+                            cswap_u(v[l], v[i]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+            if (i < n) a[i] = (T)v[i];
+        return;
+    }
+    for (int i = 1; i < n; ++i) {
+        const T x = a[i];
+        int j = i - 1;
+        while (j >= 0 && a[j] > x) {
+            a[j + 1] = a[j];
+            --j;
+        }
+        a[j + 1] = x;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // one cluster
 // ---------------------------------------------------------------------------
+// The local VT relation of every vertex in the cluster's local table is built
+// first (count, scan, scatter of stream positions); it is the one structure
+// the three relations are read from:
+//   VT  a row's list, sorted (stream order is tetrahedron id order);
+//   VV  the union of the vertices of a row's tetrahedra, through a bitmap over
+//       the local table, which is in original id order;
+//   TT  the tetrahedra sharing a face of an internal tetrahedron all lie in
+//       the list of each of the face's vertices: scan the shortest one.
 template <int B, bool kL>
 __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterMeta &m, const Plan &pl,
                               char *smem, char *ws) {
     using PosT = typename std::conditional<kL, uint16_t, int32_t>::type;
-    using RowT = typename std::conditional<kL, int16_t, int32_t>::type;
-    using SlotT = typename std::conditional<kL, uint32_t, unsigned long long>::type;
-    constexpr int kRefBits = kL ? 16 : 32;
-    constexpr SlotT kRefMask = kL ? (SlotT)0xFFFFu : (SlotT)0xFFFFFFFFull;
-    constexpr SlotT kEmpty = kL ? (SlotT)0xFFFFFFFFu : (SlotT)0xFFFFFFFFFFFFFFFFull;
+    using LidT = typename std::conditional<kL, uint16_t, int32_t>::type;
+    constexpr int NW = B / 64;
 
     __shared__ int s_status;
+    __shared__ int s_fail;
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int ns = m.ns, nh = m.nh, ntot = ns + nh, nT = m.nT, L = m.L, nV = m.nV;
     const uint32_t mask = it.mask;
-    const int4 *tg = a.s.tets + m.tet_off;
+    const char *tb = a.s.tets + m.tb_off;
+    const bool wide = (m.flags & kMetaWide) != 0;
     const int32_t *idg = a.s.tid + m.tet_off;
     const int32_t *lvg = a.s.lverts + m.lv_off;
     int32_t *blk = a.out + it.out_word;
     const BlockLayout lay = block_layout(mask, nV, nT, m.nnzVT, it.cap_vv, it.cap_tt);
     char *base = kL ? smem : ws;
 
-    ushort4 *lt = reinterpret_cast<ushort4 *>(smem + pl.tets);
-    unsigned long long *ib = reinterpret_cast<unsigned long long *>(smem + pl.ibits);
+    ushort4 *lt = reinterpret_cast<ushort4 *>(smem + pl.lt);
+    unsigned long long *ib = reinterpret_cast<unsigned long long *>(base + pl.ib);
+    int32_t *ibp = reinterpret_cast<int32_t *>(base + pl.ibp);
+    int32_t *cnt = reinterpret_cast<int32_t *>(base + pl.cnt);
+    PosT *lvt = reinterpret_cast<PosT *>(base + pl.lvt);
+    LidT *rowl = reinterpret_cast<LidT *>(base + pl.rowl);
+    uint32_t *wbm = reinterpret_cast<uint32_t *>(base + pl.wbm);
 
-    if (tid == 0) s_status = 0;
+    if (tid == 0) {
+        s_status = 0;
+        s_fail = 0;
+    }
 #ifdef GALE_PHASE_TIMING
     unsigned long long phase_t0 = __builtin_amdgcn_s_memtime();
 #endif
 
     auto tet = [&](int p) -> int4 {
         if constexpr (kL) {
-            ushort4 q = lt[p];
+            const ushort4 q = lt[p];
             return make_int4(q.x, q.y, q.z, q.w);
         } else {
-            return tg[p];
+            if (wide) return reinterpret_cast<const int4 *>(tb)[p];
+            const ushort4 q = reinterpret_cast<const ushort4 *>(tb)[p];
+            return make_int4(q.x, q.y, q.z, q.w);
         }
     };
-    auto internal = [&](int p) -> bool {
-        if constexpr (kL) {
-            return p < ns && ((ib[p >> 6] >> (p & 63)) & 1ull);
-        } else {
-            return p < ns && idg[p] < 0;
-        }
-    };
+    auto internal = [&](int p) -> bool { return p < ns && ((ib[p >> 6] >> (p & 63)) & 1ull); };
 
-    // ---- stage the stream in LDS ---------------------------------------
+    // ---- stage the stream in LDS; zero the local VT counters --------------
     if constexpr (kL) {
-        for (int p = tid; p < ntot; p += B) {
-            int4 t = tg[p];
-            lt[p] = make_ushort4((unsigned short)t.x, (unsigned short)t.y, (unsigned short)t.z,
-                                 (unsigned short)t.w);
-        }
-        if (mask & kRelTT) {
-            const int lane = tid & 63, wid = tid >> 6;
-            const int nwords = (ns + 63) >> 6;
-            for (int w = wid; w < nwords; w += B / 64) {
-                const int p = w * 64 + lane;
-                const bool f = p < ns && idg[p] < 0;
-                const unsigned long long bits = __ballot(f);
-                if (lane == 0) ib[w] = bits;
+        // the LDS path only takes 4 x uint16 streams; copy 16 B (two tetrahedra)
+        // per load, the stream and lt both padded to 16 B
+        constexpr int U = 8;
+        const int nq = (ntot + 1) >> 1;
+        const uint4 *src = reinterpret_cast<const uint4 *>(tb);
+        uint4 *dst = reinterpret_cast<uint4 *>(lt);
+        for (int i0 = 0; i0 < nq; i0 += B * U) {
+            uint4 t[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * B + tid;
+                t[u] = i < nq ? src[i] : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = i0 + u * B + tid;
+                if (i < nq) dst[i] = t[u];
             }
         }
     }
-    __syncthreads();
-    PHASE_MARK(0);
-
-#ifdef GALE_DEBUG_CHECKS
-    auto check_lt = [&](int bit) {
-        if constexpr (kL) {
-            for (int p = tid; p < ntot; p += B) {
-                int4 t = tg[p];
-                ushort4 q = lt[p];
-                if (q.x != (unsigned short)t.x || q.y != (unsigned short)t.y || q.z != (unsigned short)t.z ||
-                    q.w != (unsigned short)t.w)
-                    atomicOr(&s_status, bit);
-            }
+    if (mask & kRelTT) {
+        const int nwords = (ns + 63) >> 6;
+        for (int w = wave; w < nwords; w += NW) {
+            const int p = w * 64 + lane;
+            const bool f = p < ns && idg[p] < 0;
+            const unsigned long long bits = __ballot(f);
+            if (lane == 0) ib[w] = bits;
         }
-        __syncthreads();
-    };
-    check_lt(1 << 16);
-#endif
-    // ---- VT / VV ---------------------------------------------------------
-    if (mask & (kRelVT | kRelVV)) {
-        RowT *rowOf = reinterpret_cast<RowT *>(base + pl.rowof);
-        int32_t *cnt = reinterpret_cast<int32_t *>(base + pl.cnt);
-        PosT *lst = reinterpret_cast<PosT *>(base + pl.lst);
+    }
+    for (int v = tid; v <= L; v += B) cnt[v] = 0;
 
-        // local vertex -> row index; row ids
+    // rows: local id of each row, row ids of the block
+    if (mask & (kRelVT | kRelVV)) {
         int carry = 0;
         for (int i0 = 0; i0 < L; i0 += B) {
             const int i = i0 + tid;
@@ -239,288 +289,356 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
             const int f = (i < L && lv < 0) ? 1 : 0;
             int tot;
             const int ex = block_excl_scan<B>(f, tot);
-            if (i < L) {
+            if (f) {
                 const int r = carry + ex;
-                // rows past nV would mean inconsistent metadata: drop them (flagged below)
-                rowOf[i] = (f && r < nV) ? (RowT)r : (RowT)-1;
-                if (f && r < nV) blk[lay.vrows + r] = lv & kIdMask;
+                if (r < nV) {
+                    rowl[r] = (LidT)i;
+                    blk[lay.vrows + r] = lv & kIdMask;
+                }
             }
             carry += tot;
         }
         if (tid == 0 && carry != nV) s_status |= kStInconsistent;
-        for (int r = tid; r <= nV; r += B) cnt[r] = 0;
-        __syncthreads();
-        PHASE_MARK(1);
-
-        // count
-        for (int p = tid; p < ns; p += B) {
-            const int4 t = tet(p);
-            const int r0 = rowOf[t.x], r1 = rowOf[t.y], r2 = rowOf[t.z], r3 = rowOf[t.w];
-            if (r0 >= 0) atomicAdd(&cnt[r0], 1);
-            if (r1 >= 0) atomicAdd(&cnt[r1], 1);
-            if (r2 >= 0) atomicAdd(&cnt[r2], 1);
-            if (r3 >= 0) atomicAdd(&cnt[r3], 1);
-        }
-        __syncthreads();
-
-        PHASE_MARK(2);
-        // inclusive scan: cnt[r] = end of row r
-        carry = 0;
-        for (int r0 = 0; r0 < nV; r0 += B) {
-            const int r = r0 + tid;
-            const int v = r < nV ? cnt[r] : 0;
+    }
+    __syncthreads();
+    if (mask & kRelTT) {
+        // internal tetrahedra before each flag word: TT row index of a tetrahedron
+        const int nwords = (ns + 63) >> 6;
+        int carry = 0;
+        for (int w0 = 0; w0 < nwords; w0 += B) {
+            const int w = w0 + tid;
+            const int x = w < nwords ? __popcll(ib[w]) : 0;
             int tot;
-            const int ex = block_excl_scan<B>(v, tot);
-            if (r < nV) cnt[r] = carry + ex + v;
+            const int ex = block_excl_scan<B>(x, tot);
+            if (w < nwords) ibp[w] = carry + ex;
             carry += tot;
         }
-        const int nnz = carry;
-        const bool vt_ok = nnz == m.nnzVT;
+        if (tid == 0 && carry != nT) s_status |= kStInconsistent;
+    }
+    PHASE_MARK(0);
+
+    // ---- local VT over every local vertex ---------------------------------
+    for (int p = tid; p < ntot; p += B) {
+        const int4 t = tet(p);
+        atomicAdd(&cnt[t.x], 1);
+        atomicAdd(&cnt[t.y], 1);
+        atomicAdd(&cnt[t.z], 1);
+        atomicAdd(&cnt[t.w], 1);
+    }
+    __syncthreads();
+    PHASE_MARK(1);
+    {
+        int carry = 0;
+        for (int v0 = 0; v0 < L; v0 += B) {
+            const int v = v0 + tid;
+            const int x = v < L ? cnt[v] : 0;
+            int tot;
+            const int ex = block_excl_scan<B>(x, tot);
+            if (v < L) cnt[v] = carry + ex + x;  // end of the list
+            carry += tot;
+        }
         if (tid == 0) {
-            cnt[nV] = nnz;
-            if (!vt_ok) s_status |= kStInconsistent;
+            cnt[L] = carry;
+            if (carry != 4 * ntot) s_status |= kStInconsistent;
+        }
+    }
+    __syncthreads();
+    PHASE_MARK(2);
+    for (int p = tid; p < ntot; p += B) {
+        const int4 t = tet(p);
+        lvt[atomicSub(&cnt[t.x], 1) - 1] = (PosT)p;
+        lvt[atomicSub(&cnt[t.y], 1) - 1] = (PosT)p;
+        lvt[atomicSub(&cnt[t.z], 1) - 1] = (PosT)p;
+        lvt[atomicSub(&cnt[t.w], 1) - 1] = (PosT)p;
+    }
+    __syncthreads();  // cnt[v] = start of v's list, cnt[v+1] = its end
+    PHASE_MARK(3);
+
+    // ---- VT ----------------------------------------------------------------
+    if (mask & kRelVT) {
+        for (int r = tid; r < nV; r += B) {
+            const int u = rowl[r];
+            const int s0 = cnt[u];
+            sort_run(lvt + s0, cnt[u + 1] - s0);
         }
         __syncthreads();
-
-        PHASE_MARK(3);
-        // scatter stream positions; afterwards cnt[r] = start of row r
-        if (vt_ok) {
-            for (int p = tid; p < ns; p += B) {
-                const int4 t = tet(p);
-                const int r0 = rowOf[t.x], r1 = rowOf[t.y], r2 = rowOf[t.z], r3 = rowOf[t.w];
-                if (r0 >= 0) lst[atomicSub(&cnt[r0], 1) - 1] = (PosT)p;
-                if (r1 >= 0) lst[atomicSub(&cnt[r1], 1) - 1] = (PosT)p;
-                if (r2 >= 0) lst[atomicSub(&cnt[r2], 1) - 1] = (PosT)p;
-                if (r3 >= 0) lst[atomicSub(&cnt[r3], 1) - 1] = (PosT)p;
-            }
-        }
-        __syncthreads();
-
         PHASE_MARK(4);
-        if (vt_ok) {
-            // sort each row's positions (rows are short; insertion sort)
-            for (int r = tid; r < nV; r += B) {
-                const int s = cnt[r], e = cnt[r + 1];
-                for (int i = s + 1; i < e; ++i) {
-                    const PosT x = lst[i];
-                    int j = i - 1;
-                    while (j >= s && lst[j] > x) {
-                        lst[j + 1] = lst[j];
-                        --j;
+        int carry = 0;
+        for (int r0 = 0; r0 < nV; r0 += B) {
+            const int r = r0 + tid;
+            int u = 0, s0 = 0, n = 0;
+            if (r < nV) {
+                u = rowl[r];
+                s0 = cnt[u];
+                n = cnt[u + 1] - s0;
+            }
+            int tot;
+            const int ex = block_excl_scan<B>(n, tot);
+            if (r < nV) {
+                const int o = carry + ex;
+                if (o + n <= m.nnzVT) {
+                    blk[lay.vt_off + r] = o;
+                    int j = 0;
+                    for (; j + 4 <= n; j += 4) {
+                        const int32_t a0 = idg[lvt[s0 + j]], a1 = idg[lvt[s0 + j + 1]];
+                        const int32_t a2 = idg[lvt[s0 + j + 2]], a3 = idg[lvt[s0 + j + 3]];
+                        blk[lay.vt_ent + o + j] = a0 & kIdMask;
+                        blk[lay.vt_ent + o + j + 1] = a1 & kIdMask;
+                        blk[lay.vt_ent + o + j + 2] = a2 & kIdMask;
+                        blk[lay.vt_ent + o + j + 3] = a3 & kIdMask;
                     }
-                    lst[j + 1] = x;
+                    for (; j < n; ++j) blk[lay.vt_ent + o + j] = idg[lvt[s0 + j]] & kIdMask;
                 }
             }
+            carry += tot;
+        }
+        if (tid == 0) {
+            blk[lay.vt_off + nV] = carry;
+            if (carry != m.nnzVT) s_status |= kStInconsistent;
         }
         __syncthreads();
-
         PHASE_MARK(5);
-        if ((mask & kRelVT) && vt_ok) {
-            for (int r = tid; r <= nV; r += B) blk[lay.vt_off + r] = cnt[r];
-            for (int e = tid; e < nnz; e += B) blk[lay.vt_ent + e] = idg[lst[e]] & kIdMask;
-        }
+    }
 
-        PHASE_MARK(6);
-        if ((mask & kRelVV) && vt_ok) {
-            uint32_t *bm = reinterpret_cast<uint32_t *>(base + pl.bm);
-            const int rc = pl.rc, W = pl.W, Wp = pl.Wp;
-            const int cap = it.cap_vv;
-            int vcarry = 0;
-            for (int r0 = 0; r0 < nV; r0 += rc) {
-                const int nr = min(rc, nV - r0);
-                for (int w = tid; w < nr * Wp; w += B) bm[w] = 0u;
-                __syncthreads();
-                int c = 0;
-                if (tid < nr) {
-                    const int r = r0 + tid;
-                    uint32_t *row = bm + (int64_t)tid * Wp;
-                    const int s = cnt[r], e = cnt[r + 1];
-                    for (int i = s; i < e; ++i) {
-                        const int4 t = tet(lst[i]);
-                        if (rowOf[t.x] != r) row[t.x >> 5] |= 1u << (t.x & 31);
-                        if (rowOf[t.y] != r) row[t.y >> 5] |= 1u << (t.y & 31);
-                        if (rowOf[t.z] != r) row[t.z >> 5] |= 1u << (t.z & 31);
-                        if (rowOf[t.w] != r) row[t.w >> 5] |= 1u << (t.w & 31);
-                    }
-                    for (int w = 0; w < W; ++w) c += __popc(row[w]);
-                }
-                int tot;
-                const int ex = block_excl_scan<B>(c, tot);
-                if (tid < nr) {
-                    const int r = r0 + tid;
-                    int pos = vcarry + ex;
-                    blk[lay.vv_off + r] = pos;
-                    const uint32_t *row = bm + (int64_t)tid * Wp;
-                    for (int w = 0; w < W; ++w) {
-                        uint32_t bits = row[w];
-                        while (bits) {
-                            const int b = __ffs(bits) - 1;
-                            bits &= bits - 1u;
-                            if (pos < cap) blk[lay.vv_ent + pos] = lvg[w * 32 + b] & kIdMask;
-                            ++pos;
-                        }
-                    }
-                }
-                vcarry += tot;
-                __syncthreads();
+    // ---- VV: one row at a time per group of B/32 lanes, bitmap over the local table
+    if (mask & kRelVV) {
+        constexpr int NG = 32;
+        constexpr int G = B / NG;
+        const int W = pl.W;
+        const int grp = tid / G, gl = tid % G;
+        uint32_t *wb = wbm + (int64_t)grp * W;
+        const int cap = it.cap_vv;
+        for (int w = gl; w < W; w += G) wb[w] = 0u;
+        wave_fence();
+        auto set_row_bits = [&](int self, int s0, int e0) {
+            for (int i = s0 + gl; i < e0; i += G) {
+                const int4 t = tet(lvt[i]);
+                if (t.x != self) atomicOr(&wb[t.x >> 5], 1u << (t.x & 31));
+                if (t.y != self) atomicOr(&wb[t.y >> 5], 1u << (t.y & 31));
+                if (t.z != self) atomicOr(&wb[t.z >> 5], 1u << (t.z & 31));
+                if (t.w != self) atomicOr(&wb[t.w >> 5], 1u << (t.w & 31));
             }
-            if (tid == 0) {
-                blk[lay.vv_off + nV] = vcarry;
-                blk[4] = vcarry;
-                if (vcarry > cap) s_status |= kStVVOverflow;
+            wave_fence();
+        };
+        // pass 1: counts
+        for (int r = grp; r < nV; r += NG) {
+            const int u = rowl[r];
+            set_row_bits(u, cnt[u], cnt[u + 1]);
+            int c = 0;
+            for (int w = gl; w < W; w += G) {
+                c += __popc(wb[w]);
+                wb[w] = 0u;
+            }
+#pragma unroll
+            for (int d = G / 2; d >= 1; d >>= 1) c += __shfl_xor(c, d, G);
+            if (gl == 0) blk[lay.vv_off + r] = c;  // the count, turned into the offset below
+            wave_fence();
+        }
+        __syncthreads();
+        PHASE_MARK(6);
+        int carry = 0;
+        for (int r0 = 0; r0 < nV; r0 += B) {
+            const int r = r0 + tid;
+            const int x = r < nV ? blk[lay.vv_off + r] : 0;
+            int tot;
+            const int ex = block_excl_scan<B>(x, tot);
+            if (r < nV) blk[lay.vv_off + r] = carry + ex;
+            carry += tot;
+        }
+        if (tid == 0) {
+            blk[lay.vv_off + nV] = carry;
+            blk[4] = carry;
+            if (carry > cap) s_status |= kStVVOverflow;
+        }
+        __syncthreads();
+        // pass 2: emit local ids in word order (ascending original id) ...
+        if (carry <= cap) {
+            for (int r = grp; r < nV; r += NG) {
+                const int u = rowl[r];
+                set_row_bits(u, cnt[u], cnt[u + 1]);
+                int o = blk[lay.vv_off + r];
+                for (int w0 = 0; w0 < W; w0 += G) {
+                    const int w = w0 + gl;
+                    uint32_t bits = 0u;
+                    if (w < W) {
+                        bits = wb[w];
+                        wb[w] = 0u;
+                    }
+                    const int n = __popc(bits);
+                    int x = n;
+#pragma unroll
+                    for (int d = 1; d < G; d <<= 1) {
+                        const int y = __shfl_up(x, d, G);
+                        if (gl >= d) x += y;
+                    }
+                    const int tot = __shfl(x, G - 1, G);
+                    int pos = o + x - n;
+                    while (bits) {
+                        const int b = __ffs(bits) - 1;
+                        bits &= bits - 1u;
+                        blk[lay.vv_ent + pos] = w * 32 + b;
+                        ++pos;
+                    }
+                    o += tot;
+                }
+                wave_fence();
+            }
+            __syncthreads();
+            // ... then map local ids to original ids in one flat pass
+            constexpr int U = 4;
+            for (int e0 = 0; e0 < carry; e0 += B * U) {
+                int32_t l[U];
+#pragma unroll
+                for (int uu = 0; uu < U; ++uu) {
+                    const int e = e0 + uu * B + tid;
+                    l[uu] = e < carry ? blk[lay.vv_ent + e] : 0;
+                }
+#pragma unroll
+                for (int uu = 0; uu < U; ++uu) l[uu] = lvg[l[uu]];
+#pragma unroll
+                for (int uu = 0; uu < U; ++uu) {
+                    const int e = e0 + uu * B + tid;
+                    if (e < carry) blk[lay.vv_ent + e] = l[uu] & kIdMask;
+                }
             }
         }
         __syncthreads();
         PHASE_MARK(7);
     }
 
-#ifdef GALE_DEBUG_CHECKS
-    check_lt(1 << 17);
-#endif
-    // ---- TT --------------------------------------------------------------
+    // ---- TT ----------------------------------------------------------------
+    // Every internal tetrahedron finds its neighbours independently and writes
+    // them, sorted, into its own provisional window of four entries (row r at
+    // 4r; the capacity is at least 4 per row) with the count in tt_off[r]; one
+    // scan then gives the offsets and the rows are moved down in place.
     if (mask & kRelTT) {
-        SlotT *ht = reinterpret_cast<SlotT *>(base + pl.ht);
-        const uint32_t H = (uint32_t)pl.H;
         const int cap = it.cap_tt;
-        __shared__ int s_fail;
-        if (tid == 0) s_fail = 0;
-        for (uint32_t i = tid; i < H; i += B) ht[i] = kEmpty;
-        __syncthreads();
-
-        auto face_of_ref = [&](uint32_t ref) -> Face { return face_of(tet((int)(ref >> 2)), (int)(ref & 3u)); };
-
-        // attach ref as the second sharer of slot s whose first sharer has the same face
-        auto attach = [&](uint32_t s, SlotT cur, uint32_t ref) {
-            const SlotT first = cur & kRefMask;
-            while (true) {
-                if (((cur >> kRefBits) & kRefMask) != kRefMask) {
-                    s_fail = 1;  // third sharer: non-manifold face
-                    return;
-                }
-                const SlotT want = ((SlotT)ref << kRefBits) | first;
-                const SlotT got = atomicCAS(&ht[s], cur, want);
-                if (got == cur) return;
-                cur = got;
-            }
-        };
-
-        // faces of internal tetrahedra
-        if (H > 0) {
-            for (int p = tid; p < ns; p += B) {
-                if (!internal(p)) continue;
+        const bool room = cap >= 4 * nT;  // the host always sizes TT for at least 4 per row
+        for (int p = tid; p < ns && room; p += B) {
+            if (!internal(p)) continue;
+            const int row = ibp[p >> 6] + __popcll(ib[p >> 6] & ((1ull << (p & 63)) - 1ull));
+            int q0 = -1, q1 = -1, q2 = -1, q3 = -1;
+            int raw = 0;
+            {
                 const int4 t = tet(p);
-                for (int k = 0; k < 4; ++k) {
-                    const Face f = face_of(t, k);
-                    const uint32_t ref = (uint32_t)p * 4u + (uint32_t)k;
-                    uint32_t s = fast_range(face_hash(f), H);
-                    bool done = false;
-                    for (uint32_t n = 0; n < H && !done; ++n) {
-                        const SlotT cur = atomicCAS(&ht[s], kEmpty, ((SlotT)kRefMask << kRefBits) | (SlotT)ref);
-                        if (cur == kEmpty) {
-                            done = true;
-                        } else if (face_of_ref((uint32_t)(cur & kRefMask)) == f) {
-                            attach(s, cur, ref);
-                            done = true;
-                        } else {
-                            s = (s + 1 == H) ? 0 : s + 1;
+                // Faces omitting t.z or t.w both hold the edge (t.x, t.y); faces
+                // omitting t.x or t.y both hold (t.z, t.w).  The tetrahedra
+                // around an edge are the entries of one endpoint's list that hold
+                // the other endpoint: scan the shorter list of each edge, keep
+                // those, and sort them to faces by the remaining two vertices.
+                const int sx = cnt[t.x], ex = cnt[t.x + 1], sy = cnt[t.y], ey = cnt[t.y + 1];
+                const int sz = cnt[t.z], ez = cnt[t.z + 1], sw = cnt[t.w], ew = cnt[t.w + 1];
+                // branch-free selects keep the four slots in registers
+                auto record = [&](int q) {
+                    q0 = raw == 0 ? q : q0;
+                    q1 = raw == 1 ? q : q1;
+                    q2 = raw == 2 ? q : q2;
+                    q3 = raw == 3 ? q : q3;
+                    ++raw;
+                };
+                auto edge = [&](int st, int en, int other, int f0, int f1) {
+                    auto visit = [&](int q, int4 tq) {
+                        if (q != p && has_vertex(tq, other)) {
+                            if (has_vertex(tq, f0)) record(q);
+                            if (has_vertex(tq, f1)) record(q);
                         }
+                    };
+                    int i = st;
+                    for (; i + 4 <= en; i += 4) {
+                        const int qa = lvt[i], qb = lvt[i + 1], qc = lvt[i + 2], qd = lvt[i + 3];
+                        const int4 ta = tet(qa), tb2 = tet(qb), tc = tet(qc), td = tet(qd);
+                        visit(qa, ta);
+                        visit(qb, tb2);
+                        visit(qc, tc);
+                        visit(qd, td);
                     }
-                    if (!done) s_fail = 1;  // table full
-                }
+                    for (; i < en; ++i) {
+                        const int q = lvt[i];
+                        visit(q, tet(q));
+                    }
+                };
+                if (ex - sx <= ey - sy) edge(sx, ex, t.y, t.z, t.w);
+                else edge(sy, ey, t.x, t.z, t.w);
+                if (ez - sz <= ew - sw) edge(sz, ez, t.w, t.x, t.y);
+                else edge(sw, ew, t.z, t.x, t.y);
+                if (raw > 4) s_fail = 1;  // a face shared by three or more tetrahedra: exhaustive path
+            }
+            int n0 = q0 >= 0 ? idg[q0] & kIdMask : 0x7fffffff;
+            int n1 = q1 >= 0 ? idg[q1] & kIdMask : 0x7fffffff;
+            int n2 = q2 >= 0 ? idg[q2] & kIdMask : 0x7fffffff;
+            int n3 = q3 >= 0 ? idg[q3] & kIdMask : 0x7fffffff;
+            cswap(n0, n1); cswap(n2, n3); cswap(n0, n2); cswap(n1, n3); cswap(n1, n2);
+            // a duplicated tetrahedron is reached through several faces: list it once
+            if (n3 == n2) n3 = 0x7fffffff;
+            if (n2 == n1) { n2 = n3; n3 = 0x7fffffff; }
+            if (n1 == n0) { n1 = n2; n2 = n3; n3 = 0x7fffffff; }
+            const int c = (n0 != 0x7fffffff) + (n1 != 0x7fffffff) + (n2 != 0x7fffffff) + (n3 != 0x7fffffff);
+            if (row < nT && room) {
+                blk[lay.trows + row] = idg[p] & kIdMask;
+                blk[lay.tt_off + row] = c;
+                int32_t *w = blk + lay.tt_ent + 4 * (int64_t)row;
+                if (c > 0) w[0] = n0;
+                if (c > 1) w[1] = n1;
+                if (c > 2) w[2] = n2;
+                if (c > 3) w[3] = n3;
             }
         }
         __syncthreads();
-
+        int rcarry = nT, ecarry = 0;
+        const bool exhaustive = s_fail || !room;
+        if (!exhaustive) {
+            for (int r0 = 0; r0 < nT; r0 += B) {
+                const int r = r0 + tid;
+                int c = 0, e0 = 0, e1 = 0, e2 = 0, e3 = 0;
+                if (r < nT) {
+                    c = blk[lay.tt_off + r];
+                    const int32_t *w = blk + lay.tt_ent + 4 * (int64_t)r;
+                    if (c > 0) e0 = w[0];
+                    if (c > 1) e1 = w[1];
+                    if (c > 2) e2 = w[2];
+                    if (c > 3) e3 = w[3];
+                }
+                int tot;
+                const int ex = block_excl_scan<B>(c, tot);  // its barriers order every read before the writes
+                if (r < nT) {
+                    const int o = ecarry + ex;
+                    blk[lay.tt_off + r] = o;
+                    int32_t *w = blk + lay.tt_ent + o;
+                    if (c > 0) w[0] = e0;
+                    if (c > 1) w[1] = e1;
+                    if (c > 2) w[2] = e2;
+                    if (c > 3) w[3] = e3;
+                }
+                ecarry += tot;
+            }
+        }
+        __syncthreads();
         PHASE_MARK(8);
-        // faces of the other stream tetrahedra: attach where an internal face matches
-        if (H > 0) {
-            for (int p = tid; p < ntot; p += B) {
-                if (internal(p)) continue;
-                const int4 t = tet(p);
-                for (int k = 0; k < 4; ++k) {
-                    const Face f = face_of(t, k);
-                    const uint32_t ref = (uint32_t)p * 4u + (uint32_t)k;
-                    uint32_t s = fast_range(face_hash(f), H);
-                    for (uint32_t n = 0; n < H; ++n) {
-                        const SlotT cur = __atomic_load_n(&ht[s], __ATOMIC_RELAXED);
-                        if (cur == kEmpty) break;
-                        if (face_of_ref((uint32_t)(cur & kRefMask)) == f) {
-                            attach(s, cur, ref);
-                            break;
-                        }
-                        s = (s + 1 == H) ? 0 : s + 1;
+        if (exhaustive) {
+            // exhaustive pairing, rows rebuilt from scratch (non-manifold faces)
+            if (tid == 0) s_status |= kStTTFallback;
+            rcarry = 0;
+            ecarry = 0;
+            for (int p0 = 0; p0 < ns; p0 += B) {
+                const int p = p0 + tid;
+                const bool in = internal(p);
+                int c = 0;
+                int4 t = make_int4(0, 0, 0, 0);
+                if (in) {
+                    t = tet(p);
+                    for (int q = 0; q < ntot; ++q)
+                        if (q != p && shared_vertices(t, tet(q)) >= 3) ++c;
+                }
+                int rtot, etot;
+                const int rex = block_excl_scan<B>(in ? 1 : 0, rtot);
+                const int eex = block_excl_scan<B>(c, etot);
+                if (in) {
+                    const int row = rcarry + rex;
+                    int pos = ecarry + eex;
+                    if (row < nT) {
+                        blk[lay.trows + row] = idg[p] & kIdMask;
+                        blk[lay.tt_off + row] = pos;
                     }
-                }
-            }
-        }
-        __syncthreads();
-#ifdef GALE_DEBUG_CHECKS
-        check_lt(1 << 18);
-#endif
-        PHASE_MARK(9);
-        const bool fallback = s_fail != 0;
-        if (tid == 0 && fallback) s_status |= kStTTFallback;
-
-        int rcarry = 0, ecarry = 0;
-        for (int p0 = 0; p0 < ns; p0 += B) {
-            const int p = p0 + tid;
-            const bool in = internal(p);
-            int n0 = 0x7fffffff, n1 = 0x7fffffff, n2 = 0x7fffffff, n3 = 0x7fffffff;
-            int c = 0;
-            if (in && !fallback) {
-                const int4 t = tet(p);
-                int nb[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    nb[k] = 0x7fffffff;
-                    const Face f = face_of(t, k);
-                    const uint32_t myref = (uint32_t)p * 4u + (uint32_t)k;
-                    uint32_t s = fast_range(face_hash(f), H);
-                    for (uint32_t n = 0; n < H; ++n) {
-                        const SlotT cur = ht[s];
-                        if (cur == kEmpty) break;
-                        const uint32_t first = (uint32_t)(cur & kRefMask);
-                        const uint32_t second = (uint32_t)((cur >> kRefBits) & kRefMask);
-                        if (first == myref) {
-                            if (second != (uint32_t)kRefMask) nb[k] = idg[second >> 2] & kIdMask;
-                            break;
-                        }
-                        if (face_of_ref(first) == f) {
-                            nb[k] = idg[first >> 2] & kIdMask;
-                            break;
-                        }
-                        s = (s + 1 == H) ? 0 : s + 1;
-                    }
-                }
-                n0 = nb[0]; n1 = nb[1]; n2 = nb[2]; n3 = nb[3];
-                cswap(n0, n1); cswap(n2, n3); cswap(n0, n2); cswap(n1, n3); cswap(n1, n2);
-                // drop repeats (a duplicated tetrahedron shares several faces) and missing
-                if (n3 == n2) n3 = 0x7fffffff;
-                if (n2 == n1) { n2 = n3; n3 = 0x7fffffff; }
-                if (n1 == n0) { n1 = n2; n2 = n3; n3 = 0x7fffffff; }
-                c = (n0 != 0x7fffffff) + (n1 != 0x7fffffff) + (n2 != 0x7fffffff) + (n3 != 0x7fffffff);
-            } else if (in) {
-                const int4 t = tet(p);
-                for (int q = 0; q < ntot; ++q)
-                    if (q != p && shared_vertices(t, tet(q)) >= 3) ++c;
-            }
-            int rtot, etot;
-            const int rex = block_excl_scan<B>(in ? 1 : 0, rtot);
-            const int eex = block_excl_scan<B>(c, etot);
-            if (in) {
-                const int row = rcarry + rex;
-                int pos = ecarry + eex;
-                if (row < nT) {
-                    blk[lay.trows + row] = idg[p] & kIdMask;
-                    blk[lay.tt_off + row] = pos;
-                }
-                if (!fallback) {
-                    if (c > 0 && pos + 0 < cap) blk[lay.tt_ent + pos + 0] = n0;
-                    if (c > 1 && pos + 1 < cap) blk[lay.tt_ent + pos + 1] = n1;
-                    if (c > 2 && pos + 2 < cap) blk[lay.tt_ent + pos + 2] = n2;
-                    if (c > 3 && pos + 3 < cap) blk[lay.tt_ent + pos + 3] = n3;
-                } else {
-                    const int4 t = tet(p);
                     const int start = pos;
                     for (int q = 0; q < ntot; ++q) {
                         if (q != p && shared_vertices(t, tet(q)) >= 3) {
@@ -540,9 +658,9 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
                         blk[lay.tt_ent + j + 1] = x;
                     }
                 }
+                rcarry += rtot;
+                ecarry += etot;
             }
-            rcarry += rtot;
-            ecarry += etot;
         }
         if (tid == 0) {
             blk[lay.tt_off + (rcarry <= nT ? rcarry : nT)] = ecarry;
@@ -550,7 +668,7 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
             if (rcarry != nT) s_status |= kStInconsistent;
             if (ecarry > cap) s_status |= kStTTOverflow;
         }
-        PHASE_MARK(10);
+        PHASE_MARK(9);
     }
     __syncthreads();
 
@@ -565,10 +683,6 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
         h[5] = (mask & kRelTT) ? blk[5] : 0;
         h[6] = it.cap_vv;
         h[7] = it.cap_tt;
-#ifdef GALE_DEBUG_CHECKS
-        h[6] = (int32_t)pl.ht | (kL ? (1 << 30) : 0);
-        h[7] = (int32_t)pl.rowof;
-#endif
         for (int i = 0; i < 8; ++i) blk[i] = h[i];
         if (a.hdr)
             for (int i = 0; i < 8; ++i) a.hdr[(int64_t)it.hdr_index * 8 + i] = h[i];
@@ -576,20 +690,25 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
     __syncthreads();
 }
 
-template <int B>
+// One work item on the LDS path (kL) or the global-workspace path.  The host
+// sorts items by path with the same plan functions; an item that does not
+// fit what it was sent to is reported in its header and skipped.
+template <int B, bool kL>
 __device__ void process_item(const KArgs &a, const WorkItem &it, char *smem, char *ws) {
     const ClusterMeta m = a.s.meta[it.cluster];
     const Plan lp = lds_plan(m, it.mask, a.lds_budget, B);
-    if (lp.ok) {
-        build_cluster<B, true>(a, it, m, lp, smem, ws);
-    } else if (ws == nullptr) {
-        // the host sizes the workspace from the same plan; without it, report and skip
+    const bool ok = kL ? (lp.ok != 0) : (ws != nullptr);
+    if (!ok) {
         if (threadIdx.x == 0) {
             int32_t *blk = a.out + it.out_word;
             blk[0] = kStInconsistent;
             if (a.hdr) a.hdr[(int64_t)it.hdr_index * 8] = kStInconsistent;
         }
         __syncthreads();
+        return;
+    }
+    if constexpr (kL) {
+        build_cluster<B, true>(a, it, m, lp, smem, ws);
     } else {
         const Plan gp = ws_plan(m, it.mask, B);
         build_cluster<B, false>(a, it, m, gp, smem, ws);
@@ -598,18 +717,18 @@ __device__ void process_item(const KArgs &a, const WorkItem &it, char *smem, cha
 
 // One work item per workgroup: item blockIdx.x.  Used for the per-cluster
 // (plain) form, one launch per (cluster, relation).
-template <int B>
+template <int B, bool kL>
 __global__ __launch_bounds__(B) void gale_items_kernel(KArgs a) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int i = blockIdx.x;
     if (i >= a.nitems) return;
     char *ws = a.ws ? a.ws + (int64_t)blockIdx.x * a.ws_stride : nullptr;
-    process_item<B>(a, a.items[i], smem, ws);
+    process_item<B, kL>(a, a.items[i], smem, ws);
 }
 
 // Persistent form: each workgroup takes the next item from the device work
 // queue until the list is exhausted (every workgroup reaches the exit test).
-template <int B>
+template <int B, bool kL>
 __global__ __launch_bounds__(B) void gale_persistent_kernel(KArgs a) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ int s_idx;
@@ -620,48 +739,59 @@ __global__ __launch_bounds__(B) void gale_persistent_kernel(KArgs a) {
         const int idx = s_idx;
         __syncthreads();
         if (idx >= a.nitems) break;
-        process_item<B>(a, a.items[idx], smem, ws);
+        process_item<B, kL>(a, a.items[idx], smem, ws);
     }
 }
 
 // ---------------------------------------------------------------------------
 // host-side launch wrappers
 // ---------------------------------------------------------------------------
-hipError_t launch_items(const KArgs &a, int block_threads, int grid, size_t lds, hipStream_t st) {
+template <bool kL>
+static hipError_t launch_items_t(const KArgs &a, int block_threads, int grid, size_t lds, hipStream_t st) {
     if (block_threads == 1024) {
-        hipLaunchKernelGGL(gale_items_kernel<1024>, dim3(grid), dim3(1024), lds, st, a);
+        hipLaunchKernelGGL((gale_items_kernel<1024, kL>), dim3(grid), dim3(1024), lds, st, a);
     } else if (block_threads == 512) {
-        hipLaunchKernelGGL(gale_items_kernel<512>, dim3(grid), dim3(512), lds, st, a);
+        hipLaunchKernelGGL((gale_items_kernel<512, kL>), dim3(grid), dim3(512), lds, st, a);
     } else {
-        hipLaunchKernelGGL(gale_items_kernel<256>, dim3(grid), dim3(256), lds, st, a);
+        hipLaunchKernelGGL((gale_items_kernel<256, kL>), dim3(grid), dim3(256), lds, st, a);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_persistent(const KArgs &a, int block_threads, int grid, size_t lds, hipStream_t st) {
+template <bool kL>
+static hipError_t launch_persistent_t(const KArgs &a, int block_threads, int grid, size_t lds, hipStream_t st) {
     if (block_threads == 1024) {
-        hipLaunchKernelGGL(gale_persistent_kernel<1024>, dim3(grid), dim3(1024), lds, st, a);
+        hipLaunchKernelGGL((gale_persistent_kernel<1024, kL>), dim3(grid), dim3(1024), lds, st, a);
     } else if (block_threads == 512) {
-        hipLaunchKernelGGL(gale_persistent_kernel<512>, dim3(grid), dim3(512), lds, st, a);
+        hipLaunchKernelGGL((gale_persistent_kernel<512, kL>), dim3(grid), dim3(512), lds, st, a);
     } else {
-        hipLaunchKernelGGL(gale_persistent_kernel<256>, dim3(grid), dim3(256), lds, st, a);
+        hipLaunchKernelGGL((gale_persistent_kernel<256, kL>), dim3(grid), dim3(256), lds, st, a);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_items(const KArgs &a, bool lds_path, int block_threads, int grid, size_t lds, hipStream_t st) {
+    return lds_path ? launch_items_t<true>(a, block_threads, grid, lds, st)
+                    : launch_items_t<false>(a, block_threads, grid, 0, st);
+}
+
+hipError_t launch_persistent(const KArgs &a, bool lds_path, int block_threads, int grid, size_t lds,
+                             hipStream_t st) {
+    return lds_path ? launch_persistent_t<true>(a, block_threads, grid, lds, st)
+                    : launch_persistent_t<false>(a, block_threads, grid, 0, st);
 }
 
 hipError_t set_lds_limits(size_t lds) {
-    hipError_t e;
-    e = hipFuncSetAttribute((const void *)gale_items_kernel<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)gale_items_kernel<512>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)gale_persistent_kernel<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)gale_items_kernel<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)gale_persistent_kernel<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)gale_persistent_kernel<512>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const void *fns[] = {
+        (const void *)gale_items_kernel<256, true>,       (const void *)gale_items_kernel<512, true>,
+        (const void *)gale_items_kernel<1024, true>,      (const void *)gale_persistent_kernel<256, true>,
+        (const void *)gale_persistent_kernel<512, true>,  (const void *)gale_persistent_kernel<1024, true>,
+    };
+    for (const void *f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 #ifdef GALE_PHASE_TIMING
@@ -675,12 +805,19 @@ extern "C" int gale_debug_phase_cycles(unsigned long long *out, int reset) {
 }
 #endif
 
-hipError_t persistent_occupancy(int block_threads, size_t lds, int *blocks_per_cu) {
+hipError_t persistent_occupancy(int block_threads, bool lds_path, size_t lds, int *blocks_per_cu) {
+    if (lds_path) {
+        if (block_threads == 1024)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<1024, true>, 1024, lds);
+        if (block_threads == 512)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<512, true>, 512, lds);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<256, true>, 256, lds);
+    }
     if (block_threads == 1024)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<1024>, 1024, lds);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<1024, false>, 1024, 0);
     if (block_threads == 512)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<512>, 512, lds);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<256>, 256, lds);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<512, false>, 512, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<256, false>, 256, 0);
 }
 
 }  // namespace gale

@@ -8,8 +8,10 @@
 //                                vertex of star(C), halo(C) and C itself, in
 //                                ascending original id; bit 31 set when the
 //                                vertex belongs to C (a VT/VV row).
-//   tets[tet_off .. +ns+nh)      int4: the four local vertex ids of each stream
-//                                tetrahedron; first the ns tetrahedra of
+//   tets (bytes from tb_off)     the four local vertex ids of each stream
+//                                tetrahedron, as 4 x uint16 (8 B) when the
+//                                local table has at most 65535 vertices, else
+//                                as 4 x int32 (16 B, flag bit 0); first the ns tetrahedra of
 //                                star(C) (at least one vertex in C) in ascending
 //                                original id, then the nh halo tetrahedra
 //                                (no vertex in C, sharing a triangle with a
@@ -49,8 +51,9 @@ constexpr int kStTTFallback = 8;   // face table could not pair every face (non-
                                    // TT was built by the exhaustive path instead (informational)
 
 struct ClusterMeta {
-    int64_t tet_off;  // first stream tetrahedron of the cluster
+    int64_t tet_off;  // first stream tetrahedron of the cluster (index into tid)
     int64_t lv_off;   // first local vertex of the cluster
+    int64_t tb_off;   // byte offset of the cluster's tetrahedra in the stream (16-aligned)
     int32_t ns;       // star(C) tetrahedra
     int32_t nh;       // halo tetrahedra
     int32_t nT;       // tetrahedra internal to C (TT rows)
@@ -58,9 +61,11 @@ struct ClusterMeta {
     int32_t nV;       // vertices of C (VT/VV rows)
     int32_t nnzVT;    // sum over rows of |VT(v)|, exact
     int32_t cap_vv;   // default VV capacity: sum over rows of min(deg+2, 3 deg, L-1)
-    int32_t pad;
+    int32_t flags;    // bit 0: tetrahedra stored as 4 x int32
+    int64_t pad;
 };
-static_assert(sizeof(ClusterMeta) == 48, "ClusterMeta layout");
+static_assert(sizeof(ClusterMeta) == 64, "ClusterMeta layout");
+constexpr int32_t kMetaWide = 1;
 
 struct WorkItem {
     int64_t out_word;  // block start (words) in the output buffer
@@ -79,7 +84,7 @@ struct BlockLayout {
 };
 
 struct Streams {
-    const int4 *tets;        // 4 local vertex ids per stream tetrahedron
+    const char *tets;        // stream tetrahedra (see ClusterMeta::tb_off, flags)
     const int32_t *tid;      // original tetrahedron id | internal << 31
     const int32_t *lverts;   // original vertex id | row << 31
     const ClusterMeta *meta;
@@ -123,109 +128,83 @@ GALE_HD BlockLayout block_layout(uint32_t mask, int32_t nV, int32_t nT, int32_t 
     return b;
 }
 
-// Slots of the TT face table: ~3.2 per internal tetrahedron (the unique faces
-// of a cluster's internal tetrahedra are ~2.2 per tetrahedron in a manifold
-// mesh; at most 4), rounded to 64.
-GALE_HD int32_t face_table_slots(int32_t nT) {
-    if (nT <= 0) return 0;
-    int64_t h = ((int64_t)nT * 16 + 4) / 5;
-    return (int32_t)((h + 63) / 64 * 64);
-}
-
 // Where each working array lives, as byte offsets from the base of the LDS
 // (LDS path) or of the workgroup's global workspace slice (global path).
+//   lt    stream tetrahedra, 4 x uint16 local ids           (LDS path only)
+//   ib    internal flag of each star tetrahedron, 1 bit
+//   ibp   internal tetrahedra before each 64-bit word of ib (TT row index)
+//   cnt   local VT offsets, one per local vertex + 1
+//   lvt   local VT entries: stream positions, 4 per stream tetrahedron
+//   rowl  local id of each row (vertex of the cluster)
+//   wbm   one bitmap over the local vertex table per row group (VV; 32 groups)
 struct Plan {
-    int32_t ok;        // LDS path possible within the budget
-    int32_t rc;        // VV rows per bitmap pass
-    int32_t W, Wp;     // bitmap words per row, padded to an odd stride
-    int32_t H;         // face table slots
-    int64_t tets, ibits, rowof, cnt, lst, bm, ht;
+    int32_t ok;       // LDS path possible within the budget
+    int32_t W;        // bitmap words per row
+    int64_t lt, ib, ibp, cnt, lvt, rowl, wbm;
     int64_t bytes;
 };
 
 GALE_HD int64_t align16(int64_t b) { return (b + 15) / 16 * 16; }
 
-// LDS path: tetrahedra staged as 4 x uint16 local ids (8 B), internal flags as
-// bits, rowOf int16, list positions uint16, face table slots 2 x uint16.
-// Every field is assigned on every path and ok is decided last (no early
-// return), so all callers see the same offsets whatever the mask.
+// LDS path: uint16 local ids and stream positions.  Offsets are assigned on
+// every path with no early return (the same offsets for every mask).
 GALE_HD Plan lds_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32_t block_threads) {
     Plan p{};
     const int64_t ntot = (int64_t)m.ns + m.nh;
-    const bool narrow = m.L <= 65535 && m.nV <= 32767 && ntot <= 16383;
-    const bool want_tt = (mask & kRelTT) != 0;
-    const bool want_v = (mask & (kRelVT | kRelVV)) != 0;
-    const bool want_vv = (mask & kRelVV) != 0;
+    const bool narrow = m.L <= 65535 && ntot <= 65535;
+    const bool tt = (mask & kRelTT) != 0;
+    const bool v = (mask & (kRelVT | kRelVV)) != 0;
+    const bool vv = (mask & kRelVV) != 0;
+    const int64_t ngroups = 32;
+    (void)block_threads;
     p.W = (m.L + 31) / 32;
-    p.Wp = p.W | 1;
-    p.H = want_tt ? face_table_slots(m.nT) : 0;
-    p.tets = 0;
-    p.ibits = align16(ntot * 8);
-    const int64_t region = p.ibits + (want_tt ? align16((int64_t)((m.ns + 63) / 64) * 8) : 0);
-    const int64_t bytesB = want_tt ? align16((int64_t)p.H * 4) : 0;
-    const int64_t a_rowof = 0;
-    const int64_t a_cnt = a_rowof + align16((int64_t)m.L * 2);
-    const int64_t a_lst = a_cnt + align16(((int64_t)m.nV + 1) * 4);
-    const int64_t a_bm = a_lst + align16((int64_t)m.nnzVT * 2);
-    p.rowof = region + a_rowof;
-    p.cnt = region + a_cnt;
-    p.lst = region + a_lst;
-    p.bm = region + a_bm;
-    p.ht = region;
-    // VV rows per bitmap pass: the largest of min(nV, block), halved down to
-    // 16, whose bitmap fits next to the lists
-    int32_t rc = 0;
-    bool rc_ok = true;
-    if (want_vv) {
-        rc = m.nV < block_threads ? m.nV : block_threads;
-        rc_ok = rc == 0;
-        while (rc > 0) {
-            const int64_t need = region + a_bm + align16((int64_t)rc * p.Wp * 4);
-            if (need <= budget) {
-                rc_ok = true;
-                break;
-            }
-            if (rc <= 16) break;
-            rc = rc / 2;
-        }
-    }
-    p.rc = rc;
-    const int64_t bytesA = want_v ? a_bm + (want_vv ? align16((int64_t)rc * p.Wp * 4) : 0) : 0;
-    p.bytes = region + (bytesA > bytesB ? bytesA : bytesB);
-    p.ok = (narrow && rc_ok && p.bytes <= budget) ? 1 : 0;
+    int64_t off = 0;
+    p.lt = off;
+    off += align16(ntot * 8);
+    p.ib = off;
+    off += tt ? align16((int64_t)((m.ns + 63) / 64) * 8) : 0;
+    p.ibp = off;
+    off += tt ? align16((int64_t)((m.ns + 63) / 64) * 4) : 0;
+    p.cnt = off;
+    off += align16(((int64_t)m.L + 1) * 4);
+    p.lvt = off;
+    off += align16(ntot * 4 * 2);
+    p.rowl = off;
+    off += v ? align16((int64_t)m.nV * 2) : 0;
+    p.wbm = off;
+    off += vv ? align16(ngroups * (int64_t)p.W * 4) : 0;
+    p.bytes = off;
+    p.ok = (narrow && off <= budget) ? 1 : 0;
     return p;
 }
 
-// Global path: the same arrays in the workgroup's workspace slice, 32-bit
-// types, face table slots 2 x uint32; tetrahedra read from the stream.
+// Global path: the same arrays (minus the staged stream and flag bits) in the
+// workgroup's workspace slice, with 32-bit entries.
 GALE_HD Plan ws_plan(const ClusterMeta &m, uint32_t mask, int32_t block_threads) {
     Plan p{};
+    const int64_t ntot = (int64_t)m.ns + m.nh;
+    const bool v = (mask & (kRelVT | kRelVV)) != 0;
+    const bool vv = (mask & kRelVV) != 0;
+    const int64_t ngroups = 32;
+    (void)block_threads;
     p.ok = 1;
     p.W = (m.L + 31) / 32;
-    p.Wp = p.W | 1;
-    p.H = (mask & kRelTT) ? face_table_slots(m.nT) : 0;
-    p.tets = 0;
-    p.ibits = 0;
-    int64_t bytesA = 0;
-    int32_t rc = 0;
-    if (mask & (kRelVT | kRelVV)) {
-        p.rowof = 0;
-        int64_t a = align16((int64_t)m.L * 4);
-        p.cnt = a;
-        a += align16(((int64_t)m.nV + 1) * 4);
-        p.lst = a;
-        a += align16((int64_t)m.nnzVT * 4);
-        p.bm = a;
-        if (mask & kRelVV) {
-            rc = m.nV < block_threads ? m.nV : block_threads;
-            a += align16((int64_t)rc * p.Wp * 4);
-        }
-        bytesA = a;
-    }
-    p.rc = rc;
-    p.ht = 0;
-    int64_t bytesB = (mask & kRelTT) ? align16((int64_t)p.H * 8) : 0;
-    p.bytes = bytesA > bytesB ? bytesA : bytesB;
+    int64_t off = 0;
+    const bool tt = (mask & kRelTT) != 0;
+    p.lt = 0;
+    p.ib = off;
+    off += tt ? align16((int64_t)((m.ns + 63) / 64) * 8) : 0;
+    p.ibp = off;
+    off += tt ? align16((int64_t)((m.ns + 63) / 64) * 4) : 0;
+    p.cnt = off;
+    off += align16(((int64_t)m.L + 1) * 4);
+    p.lvt = off;
+    off += align16(ntot * 4 * 4);
+    p.rowl = off;
+    off += v ? align16((int64_t)m.nV * 4) : 0;
+    p.wbm = off;
+    off += vv ? align16(ngroups * (int64_t)p.W * 4) : 0;
+    p.bytes = off;
     return p;
 }
 

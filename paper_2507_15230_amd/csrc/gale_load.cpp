@@ -330,14 +330,19 @@ gale_status prepare_streams(int32_t nv, int64_t nt, const int32_t *tv, const int
         err = "a cluster exceeds the 2^31 entries limit of one block";
         return GALE_EINVAL;
     }
-    int64_t tetn = 0, lvn = 0;
+    int64_t tetn = 0, lvn = 0, tbn = 0;
     for (int32_t k = 0; k < ncl; ++k) {
-        out.meta[k].tet_off = tetn;
-        out.meta[k].lv_off = lvn;
-        tetn += (int64_t)out.meta[k].ns + out.meta[k].nh;
-        lvn += out.meta[k].L;
+        ClusterMeta &m = out.meta[k];
+        const int64_t ntot = (int64_t)m.ns + m.nh;
+        m.flags = m.L > 65535 ? kMetaWide : 0;
+        m.tet_off = tetn;
+        m.lv_off = lvn;
+        m.tb_off = tbn;
+        tetn += ntot;
+        lvn += m.L;
+        tbn += (ntot * ((m.flags & kMetaWide) ? 16 : 8) + 15) / 16 * 16;
     }
-    out.tets.assign((size_t)tetn * 4, 0);
+    out.tets.assign((size_t)tbn, 0);
     out.tid.assign((size_t)tetn, 0);
     out.lverts.assign((size_t)lvn, 0);
     next = 0;
@@ -357,15 +362,28 @@ gale_status prepare_streams(int32_t nv, int64_t nt, const int32_t *tv, const int
                     auto local = [&](int32_t v) -> int32_t {
                         return (int32_t)(std::lower_bound(tab.begin(), tab.end(), v) - tab.begin());
                     };
-                    int64_t p = m.tet_off;
-                    for (int64_t s = soff[k]; s < soff[k + 1]; ++s, ++p) {
+                    const bool wide = (m.flags & kMetaWide) != 0;
+                    uint8_t *tb = out.tets.data() + m.tb_off;
+                    auto put = [&](int64_t i, int32_t t) {
+                        for (int j = 0; j < 4; ++j) {
+                            const int32_t l = local(tv[4 * (int64_t)t + j]);
+                            if (wide) {
+                                std::memcpy(tb + 16 * i + 4 * j, &l, 4);
+                            } else {
+                                const uint16_t l16 = (uint16_t)l;
+                                std::memcpy(tb + 8 * i + 2 * j, &l16, 2);
+                            }
+                        }
+                    };
+                    int64_t p = m.tet_off, i = 0;
+                    for (int64_t s = soff[k]; s < soff[k + 1]; ++s, ++p, ++i) {
                         const int32_t t = star[s];
-                        for (int j = 0; j < 4; ++j) out.tets[4 * p + j] = local(tv[4 * (int64_t)t + j]);
+                        put(i, t);
                         out.tid[p] = owner[t] == k ? (int32_t)((uint32_t)t | 0x80000000u) : t;
                     }
-                    for (int64_t s = hoff[k]; s < hoff[k + 1]; ++s, ++p) {
+                    for (int64_t s = hoff[k]; s < hoff[k + 1]; ++s, ++p, ++i) {
                         const int32_t t = halo[s].second;
-                        for (int j = 0; j < 4; ++j) out.tets[4 * p + j] = local(tv[4 * (int64_t)t + j]);
+                        put(i, t);
                         out.tid[p] = t;
                     }
                 }

@@ -216,7 +216,7 @@ void complete_slot(gale_ctx *ctx, Slot &sl, std::vector<int64_t> &rebuild) {
             // rebuild with exact capacities in the next batch
             arena_free(s, e.off, e.bytes);
             e.cap_vv = (e.mask & kRelVV) ? std::max(h[4], 0) : 0;
-            e.cap_tt = (e.mask & kRelTT) ? std::max(h[5], 0) : 0;
+            e.cap_tt = (e.mask & kRelTT) ? std::max(h[5], default_cap_tt(m)) : 0;
             e.bytes = round_up(block_bytes(m, e.mask, e.cap_vv, e.cap_tt), kArenaAlign);
             e.off = -1;
             rebuild.push_back(sl.keys[i]);
@@ -399,32 +399,12 @@ bool admit_round(gale_ctx *ctx, Slot &sl, std::vector<int64_t> &rebuild) {
     b.items = items;
     const int n = (int)items.size();
     hipError_t err;
-    int ng = 0;
-    const int64_t wsb = workspace_bytes(ctx, items, &ng);
-    ctx->n_global_blocks += ng;
-    const int grid = std::min<int>(n, ctx->persistent_grid);
-    b.dev_items = ctx->dev_pool.acquire((size_t)n * sizeof(WorkItem) + 64, &err);
-    b.dev_hdr = ctx->dev_pool.acquire((size_t)n * 32 + 64, &err);
-    b.host_items = ctx->pin_pool.acquire((size_t)n * sizeof(WorkItem) + 64, &err);
-    b.host_hdr = ctx->pin_pool.acquire((size_t)n * 32 + 64, &err);
-    if (wsb > 0) b.ws = ctx->dev_pool.acquire((size_t)wsb * grid, &err);
     gale_status st = GALE_OK;
-    if (!b.dev_items || !b.dev_hdr || !b.host_items || !b.host_hdr || (wsb > 0 && !b.ws)) {
-        st = fail(GALE_ENOMEM, "serving batch buffers");
-    } else {
-        char *hi = (char *)b.host_items->ptr;
-        std::memset(hi, 0, 64);
-        std::memcpy(hi + 64, items.data(), (size_t)n * sizeof(WorkItem));
-        err = hipMemcpyAsync(b.dev_items->ptr, hi, (size_t)n * sizeof(WorkItem) + 64, hipMemcpyHostToDevice,
-                             sl.stream);
-        if (err != hipSuccess) st = fail(GALE_EDEVICE, std::string("work list copy: ") + hipGetErrorString(err));
-    }
-    if (st == GALE_OK) {
-        char *di = (char *)b.dev_items->ptr;
-        st = launch_batch(ctx, GALE_FORM_BATCHED, (int32_t *)s.arena, (int32_t *)b.dev_hdr->ptr,
-                          (const WorkItem *)(di + 64), n, (int32_t *)di, b.ws ? (char *)b.ws->ptr : nullptr, wsb,
-                          sl.stream);
-    }
+    b.host_hdr = ctx->pin_pool.acquire((size_t)n * 32 + 64, &err);
+    if (!b.host_hdr) st = fail(GALE_ENOMEM, "serving batch buffers");
+    if (st == GALE_OK)
+        st = upload_and_launch(ctx, GALE_FORM_BATCHED, items, (int32_t *)s.arena, b.dev_items, b.dev_hdr,
+                               b.host_items, b.ws, sl.stream);
     if (st == GALE_OK) {
         err = hipEventRecord(sl.done, sl.stream);
         if (err != hipSuccess) st = fail(GALE_EDEVICE, std::string("event: ") + hipGetErrorString(err));
