@@ -218,3 +218,19 @@ def test_error_paths():
         with pytest.raises(gale.GaleError) as ei:
             ctx.load(m.tets, m.cluster, m.nclusters)
         assert ei.value.status == gale.ESTATE
+
+
+def test_refined_lognormal_clusters():
+    """Blob-refined lattice (three rounds of centroid splits on 5% of the
+    tetrahedra) with lognormal cluster capacities up to 8192: high vertex
+    valences and clusters too large for LDS (global path)."""
+    gale = _gale()
+    m = meshgen.refined_mesh(36, 0.05, 3, 512, 1.0, seed=11)
+    _say("refined", m.nv, m.nt, m.nclusters)
+    orc = oracle.Oracle.of(m)
+    for form in ("batched", "plain"):
+        with gale.Context(form=form) as ctx:
+            ctx.load(m.tets, m.cluster, m.nclusters)
+            compare_all(ctx, m, orc)
+            st = ctx.stats()
+            _say(form, "global-path blocks", st["global_path_blocks"], "exhaustive TT", st["tt_exhaustive_blocks"])
