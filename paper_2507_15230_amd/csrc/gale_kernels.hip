@@ -8,11 +8,11 @@
 // for the LDS budget, in a per-workgroup slice of global memory (same
 // algorithm, 32-bit types).
 //
-// All three relations are read from one structure built first: the local VT
-// relation of every vertex of the cluster's local table (count per vertex with
-// LDS atomics, inclusive scan, scatter of stream positions with atomic
-// decrements).  No global atomics are used (the paper's VT kernel is limited
-// by atomics on one vertex, Appendix A.1).
+// VT and VV are read from one structure: the local VT relation of every
+// vertex of the cluster's local table (count per vertex with LDS atomics,
+// inclusive scan, scatter of stream positions with atomic decrements).  No
+// global atomics are used (the paper's VT kernel is limited by atomics on one
+// vertex, Appendix A.1).
 //
 // VT (Section 4.6: iterate the segment's tetrahedra, take the vertices in the
 // segment, relate them): a row's list, sorted; stream order is tetrahedron id
@@ -28,12 +28,14 @@
 // are known before any entry is written.
 //
 // TT (two tetrahedra are adjacent iff they share a triangle, Section 2.2):
-// every tetrahedron holding face {a,b,c} of an internal tetrahedron is in the
-// local VT lists of a, b and c.  The four faces of t = (x,y,z,w) hold either
-// edge xy or edge zw, so a thread scans one list per edge, keeps the
-// tetrahedra holding the edge and assigns them to faces by the two other
-// vertices.  More than four raw neighbours (a face shared by three or more
-// tetrahedra) switches the cluster to exhaustive pairing.
+// an LDS hash table keyed by the triangle (its three local ids, sorted).
+// Internal tetrahedra insert their four faces; the second to insert a face
+// pairs the two and writes each into the other's partner slot for that face.
+// The remaining stream tetrahedra then look their faces up and write
+// themselves into the internal partner's slot.  A face met a third time
+// (non-manifold) switches the cluster to exhaustive pairing.  When the table
+// is smaller than the faces, the faces are split by hash into passes.  TT
+// runs before the local VT is built and shares its LDS region.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <type_traits>
@@ -64,32 +66,37 @@ __device__ unsigned long long g_phase_cycles[32];
 // ---------------------------------------------------------------------------
 // workgroup exclusive scan (wave64 shuffles + one LDS word per wave)
 // ---------------------------------------------------------------------------
+// Two buffers of wave totals, used alternately (par flips on every call), so
+// that the next call may start writing while threads still read this one's.
 template <int B>
-__device__ __forceinline__ int block_excl_scan(int v, int &total) {
-    __shared__ int s_wave[B / 64 + 1];
+__device__ __forceinline__ int block_excl_scan(int v, int &total, int &par) {
+    constexpr int NW = B / 64;
+    __shared__ int s_wave[2][NW + 1];
+    int *sw = s_wave[par];
+    par ^= 1;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int x = v;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-        int y = __shfl_up(x, d, 64);
+        const int y = __shfl_up(x, d, 64);
         if (lane >= d) x += y;
     }
-    if (lane == 63) s_wave[wid] = x;
+    if (lane == 63) sw[wid] = x;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int s = 0;
-        for (int w = 0; w < B / 64; ++w) {
-            int t = s_wave[w];
-            s_wave[w] = s;
-            s += t;
+    if (wid == 0) {
+        const int t = lane < NW ? sw[lane] : 0;
+        int y = t;
+#pragma unroll
+        for (int d = 1; d < NW; d <<= 1) {
+            const int z = __shfl_up(y, d, 64);
+            if (lane >= d) y += z;
         }
-        s_wave[B / 64] = s;
+        if (lane < NW) sw[lane] = y - t;
+        if (lane == NW - 1) sw[NW] = y;
     }
     __syncthreads();
-    const int res = x - v + s_wave[wid];
-    total = s_wave[B / 64];
-    __syncthreads();
-    return res;
+    total = sw[NW];
+    return x - v + sw[wid];
 }
 
 // ---------------------------------------------------------------------------
@@ -119,7 +126,7 @@ __device__ __forceinline__ void wave_fence() {
 }
 
 __device__ __forceinline__ int wave_sum(int x) {
-#pragma unroll
+    #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
     return x;
 }
@@ -127,7 +134,7 @@ __device__ __forceinline__ int wave_sum(int x) {
 __device__ __forceinline__ int wave_excl_scan(int v, int &total) {
     const int lane = threadIdx.x & 63;
     int x = v;
-#pragma unroll
+    #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
         const int y = __shfl_up(x, d, 64);
         if (lane >= d) x += y;
@@ -146,69 +153,118 @@ __device__ __forceinline__ void cswap_u(uint32_t &x, uint32_t &y) {
     y = hi;
 }
 
-// Sort a[0..n) ascending in place; n <= 32 through a register bitonic network,
-// longer runs by insertion.
-template <typename T>
-__device__ __forceinline__ void sort_run(T *a, int n) {
-    if (n <= 1) return;
-    if (n <= 32) {
-        uint32_t v[32];
+// Sort 32 registers ascending (bitonic network).
+__device__ __forceinline__ void sort32(uint32_t (&v)[32]) {
 #pragma unroll
-        for (int i = 0; i < 32; ++i) v[i] = i < n ? (uint32_t)a[i] : 0xFFFFFFFFu;
+    for (int k = 2; k <= 32; k <<= 1) {
 #pragma unroll
-        for (int k = 2; k <= 32; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
 #pragma unroll
-            for (int j = k >> 1; j > 0; j >>= 1) {
-#pragma unroll
-                for (int i = 0; i < 32; ++i) {
-                    const int l = i ^ j;
-                    if (l > i) {
-                        if ((i & k) == 0)
-                            cswap_u(v[i], v[l]);
-                        else
-                            cswap_u(v[l], v[i]);
-                    }
+            for (int i = 0; i < 32; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    if ((i & k) == 0)
+                        cswap_u(v[i], v[l]);
+                    else
+                        cswap_u(v[l], v[i]);
                 }
             }
         }
-#pragma unroll
-        for (int i = 0; i < 32; ++i)
-            if (i < n) a[i] = (T)v[i];
-        return;
-    }
-    for (int i = 1; i < n; ++i) {
-        const T x = a[i];
-        int j = i - 1;
-        while (j >= 0 && a[j] > x) {
-            a[j + 1] = a[j];
-            --j;
-        }
-        a[j + 1] = x;
     }
 }
 
 // ---------------------------------------------------------------------------
 // one cluster
 // ---------------------------------------------------------------------------
-// The local VT relation of every vertex in the cluster's local table is built
-// first (count, scan, scatter of stream positions); it is the one structure
-// the three relations are read from:
-//   VT  a row's list, sorted (stream order is tetrahedron id order);
+// one cluster
+// ---------------------------------------------------------------------------
+// Cells of the face table and of the partner windows.  A cell holds 0
+// (empty) or a stream position + 1, and changes once.  LDS cells are uint16
+// (a stream on the LDS path has at most 65535 tetrahedra), accessed through
+// the 32-bit word holding two of them; global cells are uint32.
+//   read     the cell and the word holding it;
+//   try_set  an empty cell, by compare-and-swap of its word against the word
+//            read (fails when the word changed: read again);
+//   mark     a partner cell by atomic OR; true when it was already set.  A
+//            second mark means a third tetrahedron on one face, after which
+//            the windows are discarded, so what the OR leaves does not matter.
+template <bool kL>
+struct Cells;
+template <>
+struct Cells<true> {
+    using T = uint16_t;
+    __device__ static uint32_t *word(T *a, uint32_t i) { return reinterpret_cast<uint32_t *>(a) + (i >> 1); }
+    __device__ static uint32_t read(T *a, uint32_t i, uint32_t &w) {
+        w = __atomic_load_n(word(a, i), __ATOMIC_RELAXED);
+        return (w >> ((i & 1) * 16)) & 0xFFFFu;
+    }
+    __device__ static bool try_set(T *a, uint32_t i, uint32_t w, uint32_t v) {
+        return atomicCAS(word(a, i), w, w | (v << ((i & 1) * 16))) == w;
+    }
+    __device__ static bool mark(T *a, uint32_t i, uint32_t v) {
+        const int sh = (i & 1) * 16;
+        return ((atomicOr(word(a, i), v << sh) >> sh) & 0xFFFFu) != 0u;
+    }
+    __device__ static uint32_t get(const T *a, uint32_t i) { return a[i]; }
+};
+template <>
+struct Cells<false> {
+    using T = uint32_t;
+    __device__ static uint32_t read(T *a, uint32_t i, uint32_t &w) {
+        w = __atomic_load_n(a + i, __ATOMIC_RELAXED);
+        return w;
+    }
+    __device__ static bool try_set(T *a, uint32_t i, uint32_t w, uint32_t v) { return atomicCAS(a + i, w, v) == w; }
+    __device__ static bool mark(T *a, uint32_t i, uint32_t v) { return atomicOr(a + i, v) != 0u; }
+    __device__ static uint32_t get(const T *a, uint32_t i) { return a[i]; }
+};
+
+// Hash of a triangle given by its sorted local ids: a multiply-add chain
+// followed by the "lowbias32" integer finaliser (C. Wellons, 2018).
+__device__ __forceinline__ uint32_t face_hash(int a, int b, int c) {
+    uint32_t h = (uint32_t)a * 0x9E3779B1u + (uint32_t)b;
+    h = h * 0x85EBCA77u + (uint32_t)c;
+    h ^= h >> 16;
+    h *= 0x7feb352du;
+    h ^= h >> 15;
+    h *= 0x846ca68bu;
+    h ^= h >> 16;
+    return h;
+}
+
+// Face k of a tetrahedron with ascending ids s omits s[k].
+__device__ __forceinline__ void face_of(int4 s, int k, int &a, int &b, int &c) {
+    a = k == 0 ? s.y : s.x;
+    b = k <= 1 ? s.z : s.y;
+    c = k == 3 ? s.z : s.w;
+}
+
+// Which face of the tetrahedron s (ascending ids) is {a < b < c}; -1 if none.
+__device__ __forceinline__ int face_index(int4 s, int a, int b, int c) {
+    const int k = s.x != a ? 0 : s.y != b ? 1 : s.z != c ? 2 : 3;
+    int fa, fb, fc;
+    face_of(s, k, fa, fb, fc);
+    return (fa == a && fb == b && fc == c) ? k : -1;
+}
+
+// Build the requested relations of one cluster.  TT first, from the internal
+// tetrahedra staged in LDS and a face table; then, for VT / VV, the local VT
+// relation of every vertex in the cluster's local table (count, scan, scatter
+// of stream positions), from which
+//   VT  a row's list, ordered by original tetrahedron id;
 //   VV  the union of the vertices of a row's tetrahedra, through a bitmap over
-//       the local table, which is in original id order;
-//   TT  the tetrahedra sharing a face of an internal tetrahedron all lie in
-//       the list of each of the face's vertices: scan the shortest one.
+//       the local table, which is in original id order.
 template <int B, bool kL>
 __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterMeta &m, const Plan &pl,
                               char *smem, char *ws) {
     using PosT = typename std::conditional<kL, uint16_t, int32_t>::type;
     using LidT = typename std::conditional<kL, uint16_t, int32_t>::type;
-    constexpr int NW = B / 64;
 
     __shared__ int s_status;
     __shared__ int s_fail;
+    __shared__ int s_full;
+    int sp = 0;  // block scan buffer parity
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
     const int ns = m.ns, nh = m.nh, ntot = ns + nh, nT = m.nT, L = m.L, nV = m.nV;
     const uint32_t mask = it.mask;
     const char *tb = a.s.tets + m.tb_off;
@@ -218,435 +274,213 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
     int32_t *blk = a.out + it.out_word;
     const BlockLayout lay = block_layout(mask, nV, nT, m.nnzVT, it.cap_vv, it.cap_tt);
     char *base = kL ? smem : ws;
-
     ushort4 *lt = reinterpret_cast<ushort4 *>(smem + pl.lt);
-    unsigned long long *ib = reinterpret_cast<unsigned long long *>(base + pl.ib);
-    int32_t *ibp = reinterpret_cast<int32_t *>(base + pl.ibp);
-    int32_t *cnt = reinterpret_cast<int32_t *>(base + pl.cnt);
-    PosT *lvt = reinterpret_cast<PosT *>(base + pl.lvt);
-    LidT *rowl = reinterpret_cast<LidT *>(base + pl.rowl);
-    uint32_t *wbm = reinterpret_cast<uint32_t *>(base + pl.wbm);
 
     if (tid == 0) {
         s_status = 0;
         s_fail = 0;
+        s_full = 0;
     }
 #ifdef GALE_PHASE_TIMING
     unsigned long long phase_t0 = __builtin_amdgcn_s_memtime();
 #endif
 
+    // a stream tetrahedron from global memory / from wherever it is staged
+    auto tet_global = [&](int p) -> int4 {
+        if (wide) return reinterpret_cast<const int4 *>(tb)[p];
+        const ushort4 q = reinterpret_cast<const ushort4 *>(tb)[p];
+        return make_int4(q.x, q.y, q.z, q.w);
+    };
     auto tet = [&](int p) -> int4 {
         if constexpr (kL) {
             const ushort4 q = lt[p];
             return make_int4(q.x, q.y, q.z, q.w);
         } else {
-            if (wide) return reinterpret_cast<const int4 *>(tb)[p];
-            const ushort4 q = reinterpret_cast<const ushort4 *>(tb)[p];
-            return make_int4(q.x, q.y, q.z, q.w);
+            return tet_global(p);
         }
     };
-    auto internal = [&](int p) -> bool { return p < ns && ((ib[p >> 6] >> (p & 63)) & 1ull); };
-
-    // ---- stage the stream in LDS; zero the local VT counters --------------
-    if constexpr (kL) {
-        // the LDS path only takes 4 x uint16 streams; copy 16 B (two tetrahedra)
-        // per load, the stream and lt both padded to 16 B
-        constexpr int U = 8;
-        const int nq = (ntot + 1) >> 1;
-        const uint4 *src = reinterpret_cast<const uint4 *>(tb);
-        uint4 *dst = reinterpret_cast<uint4 *>(lt);
-        for (int i0 = 0; i0 < nq; i0 += B * U) {
-            uint4 t[U];
+    // copy stream tetrahedra [t0, t1) to LDS, 16 B (two tetrahedra) per load;
+    // the stream and lt are both padded to 16 B
+    auto stage = [&](int t0, int t1) {
+        if constexpr (kL) {
+            constexpr int U = 8;
+            const int q0 = t0 >> 1, q1 = (t1 + 1) >> 1;
+            const uint4 *src = reinterpret_cast<const uint4 *>(tb);
+            uint4 *dst = reinterpret_cast<uint4 *>(lt);
+            for (int i0 = q0; i0 < q1; i0 += B * U) {
+                uint4 t[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * B + tid;
-                t[u] = i < nq ? src[i] : make_uint4(0u, 0u, 0u, 0u);
-            }
+                for (int u = 0; u < U; ++u) {
+                    const int i = i0 + u * B + tid;
+                    t[u] = i < q1 ? src[i] : make_uint4(0u, 0u, 0u, 0u);
+                }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = i0 + u * B + tid;
-                if (i < nq) dst[i] = t[u];
-            }
-        }
-    }
-    if (mask & kRelTT) {
-        const int nwords = (ns + 63) >> 6;
-        for (int w = wave; w < nwords; w += NW) {
-            const int p = w * 64 + lane;
-            const bool f = p < ns && idg[p] < 0;
-            const unsigned long long bits = __ballot(f);
-            if (lane == 0) ib[w] = bits;
-        }
-    }
-    for (int v = tid; v <= L; v += B) cnt[v] = 0;
-
-    // rows: local id of each row, row ids of the block
-    if (mask & (kRelVT | kRelVV)) {
-        int carry = 0;
-        for (int i0 = 0; i0 < L; i0 += B) {
-            const int i = i0 + tid;
-            const int32_t lv = i < L ? lvg[i] : 0;
-            const int f = (i < L && lv < 0) ? 1 : 0;
-            int tot;
-            const int ex = block_excl_scan<B>(f, tot);
-            if (f) {
-                const int r = carry + ex;
-                if (r < nV) {
-                    rowl[r] = (LidT)i;
-                    blk[lay.vrows + r] = lv & kIdMask;
+                for (int u = 0; u < U; ++u) {
+                    const int i = i0 + u * B + tid;
+                    if (i < q1) dst[i] = t[u];
                 }
             }
-            carry += tot;
         }
-        if (tid == 0 && carry != nV) s_status |= kStInconsistent;
-    }
+    };
+
+    const bool want_v = (mask & (kRelVT | kRelVV)) != 0;
+    stage(0, (mask & kRelTT) ? nT : (want_v ? ns : 0));
     __syncthreads();
-    if (mask & kRelTT) {
-        // internal tetrahedra before each flag word: TT row index of a tetrahedron
-        const int nwords = (ns + 63) >> 6;
-        int carry = 0;
-        for (int w0 = 0; w0 < nwords; w0 += B) {
-            const int w = w0 + tid;
-            const int x = w < nwords ? __popcll(ib[w]) : 0;
-            int tot;
-            const int ex = block_excl_scan<B>(x, tot);
-            if (w < nwords) ibp[w] = carry + ex;
-            carry += tot;
-        }
-        if (tid == 0 && carry != nT) s_status |= kStInconsistent;
-    }
     PHASE_MARK(0);
 
-    // ---- local VT over every local vertex ---------------------------------
-    for (int p = tid; p < ntot; p += B) {
-        const int4 t = tet(p);
-        atomicAdd(&cnt[t.x], 1);
-        atomicAdd(&cnt[t.y], 1);
-        atomicAdd(&cnt[t.z], 1);
-        atomicAdd(&cnt[t.w], 1);
-    }
-    __syncthreads();
-    PHASE_MARK(1);
-    {
-        int carry = 0;
-        for (int v0 = 0; v0 < L; v0 += B) {
-            const int v = v0 + tid;
-            const int x = v < L ? cnt[v] : 0;
-            int tot;
-            const int ex = block_excl_scan<B>(x, tot);
-            if (v < L) cnt[v] = carry + ex + x;  // end of the list
-            carry += tot;
-        }
-        if (tid == 0) {
-            cnt[L] = carry;
-            if (carry != 4 * ntot) s_status |= kStInconsistent;
-        }
-    }
-    __syncthreads();
-    PHASE_MARK(2);
-    for (int p = tid; p < ntot; p += B) {
-        const int4 t = tet(p);
-        lvt[atomicSub(&cnt[t.x], 1) - 1] = (PosT)p;
-        lvt[atomicSub(&cnt[t.y], 1) - 1] = (PosT)p;
-        lvt[atomicSub(&cnt[t.z], 1) - 1] = (PosT)p;
-        lvt[atomicSub(&cnt[t.w], 1) - 1] = (PosT)p;
-    }
-    __syncthreads();  // cnt[v] = start of v's list, cnt[v+1] = its end
-    PHASE_MARK(3);
-
-    // ---- VT ----------------------------------------------------------------
-    if (mask & kRelVT) {
-        for (int r = tid; r < nV; r += B) {
-            const int u = rowl[r];
-            const int s0 = cnt[u];
-            sort_run(lvt + s0, cnt[u + 1] - s0);
-        }
-        __syncthreads();
-        PHASE_MARK(4);
-        int carry = 0;
-        for (int r0 = 0; r0 < nV; r0 += B) {
-            const int r = r0 + tid;
-            int u = 0, s0 = 0, n = 0;
-            if (r < nV) {
-                u = rowl[r];
-                s0 = cnt[u];
-                n = cnt[u + 1] - s0;
-            }
-            int tot;
-            const int ex = block_excl_scan<B>(n, tot);
-            if (r < nV) {
-                const int o = carry + ex;
-                if (o + n <= m.nnzVT) {
-                    blk[lay.vt_off + r] = o;
-                    int j = 0;
-                    for (; j + 4 <= n; j += 4) {
-                        const int32_t a0 = idg[lvt[s0 + j]], a1 = idg[lvt[s0 + j + 1]];
-                        const int32_t a2 = idg[lvt[s0 + j + 2]], a3 = idg[lvt[s0 + j + 3]];
-                        blk[lay.vt_ent + o + j] = a0 & kIdMask;
-                        blk[lay.vt_ent + o + j + 1] = a1 & kIdMask;
-                        blk[lay.vt_ent + o + j + 2] = a2 & kIdMask;
-                        blk[lay.vt_ent + o + j + 3] = a3 & kIdMask;
-                    }
-                    for (; j < n; ++j) blk[lay.vt_ent + o + j] = idg[lvt[s0 + j]] & kIdMask;
-                }
-            }
-            carry += tot;
-        }
-        if (tid == 0) {
-            blk[lay.vt_off + nV] = carry;
-            if (carry != m.nnzVT) s_status |= kStInconsistent;
-        }
-        __syncthreads();
-        PHASE_MARK(5);
-    }
-
-    // ---- VV: one row at a time per group of B/32 lanes, bitmap over the local table
-    if (mask & kRelVV) {
-        constexpr int NG = 32;
-        constexpr int G = B / NG;
-        const int W = pl.W;
-        const int grp = tid / G, gl = tid % G;
-        uint32_t *wb = wbm + (int64_t)grp * W;
-        const int cap = it.cap_vv;
-        for (int w = gl; w < W; w += G) wb[w] = 0u;
-        wave_fence();
-        auto set_row_bits = [&](int self, int s0, int e0) {
-            for (int i = s0 + gl; i < e0; i += G) {
-                const int4 t = tet(lvt[i]);
-                if (t.x != self) atomicOr(&wb[t.x >> 5], 1u << (t.x & 31));
-                if (t.y != self) atomicOr(&wb[t.y >> 5], 1u << (t.y & 31));
-                if (t.z != self) atomicOr(&wb[t.z >> 5], 1u << (t.z & 31));
-                if (t.w != self) atomicOr(&wb[t.w >> 5], 1u << (t.w & 31));
-            }
-            wave_fence();
-        };
-        // pass 1: counts
-        for (int r = grp; r < nV; r += NG) {
-            const int u = rowl[r];
-            set_row_bits(u, cnt[u], cnt[u + 1]);
-            int c = 0;
-            for (int w = gl; w < W; w += G) {
-                c += __popc(wb[w]);
-                wb[w] = 0u;
-            }
-#pragma unroll
-            for (int d = G / 2; d >= 1; d >>= 1) c += __shfl_xor(c, d, G);
-            if (gl == 0) blk[lay.vv_off + r] = c;  // the count, turned into the offset below
-            wave_fence();
-        }
-        __syncthreads();
-        PHASE_MARK(6);
-        int carry = 0;
-        for (int r0 = 0; r0 < nV; r0 += B) {
-            const int r = r0 + tid;
-            const int x = r < nV ? blk[lay.vv_off + r] : 0;
-            int tot;
-            const int ex = block_excl_scan<B>(x, tot);
-            if (r < nV) blk[lay.vv_off + r] = carry + ex;
-            carry += tot;
-        }
-        if (tid == 0) {
-            blk[lay.vv_off + nV] = carry;
-            blk[4] = carry;
-            if (carry > cap) s_status |= kStVVOverflow;
-        }
-        __syncthreads();
-        // pass 2: emit local ids in word order (ascending original id) ...
-        if (carry <= cap) {
-            for (int r = grp; r < nV; r += NG) {
-                const int u = rowl[r];
-                set_row_bits(u, cnt[u], cnt[u + 1]);
-                int o = blk[lay.vv_off + r];
-                for (int w0 = 0; w0 < W; w0 += G) {
-                    const int w = w0 + gl;
-                    uint32_t bits = 0u;
-                    if (w < W) {
-                        bits = wb[w];
-                        wb[w] = 0u;
-                    }
-                    const int n = __popc(bits);
-                    int x = n;
-#pragma unroll
-                    for (int d = 1; d < G; d <<= 1) {
-                        const int y = __shfl_up(x, d, G);
-                        if (gl >= d) x += y;
-                    }
-                    const int tot = __shfl(x, G - 1, G);
-                    int pos = o + x - n;
-                    while (bits) {
-                        const int b = __ffs(bits) - 1;
-                        bits &= bits - 1u;
-                        blk[lay.vv_ent + pos] = w * 32 + b;
-                        ++pos;
-                    }
-                    o += tot;
-                }
-                wave_fence();
-            }
-            __syncthreads();
-            // ... then map local ids to original ids in one flat pass
-            constexpr int U = 4;
-            for (int e0 = 0; e0 < carry; e0 += B * U) {
-                int32_t l[U];
-#pragma unroll
-                for (int uu = 0; uu < U; ++uu) {
-                    const int e = e0 + uu * B + tid;
-                    l[uu] = e < carry ? blk[lay.vv_ent + e] : 0;
-                }
-#pragma unroll
-                for (int uu = 0; uu < U; ++uu) l[uu] = lvg[l[uu]];
-#pragma unroll
-                for (int uu = 0; uu < U; ++uu) {
-                    const int e = e0 + uu * B + tid;
-                    if (e < carry) blk[lay.vv_ent + e] = l[uu] & kIdMask;
-                }
-            }
-        }
-        __syncthreads();
-        PHASE_MARK(7);
-    }
-
     // ---- TT ----------------------------------------------------------------
-    // Every internal tetrahedron finds its neighbours independently and writes
-    // them, sorted, into its own provisional window of four entries (row r at
-    // 4r; the capacity is at least 4 per row) with the count in tt_off[r]; one
-    // scan then gives the offsets and the rows are moved down in place.
+    // Internal tetrahedra (stream positions 0..nT-1, the rows) enter their four
+    // faces in the table; the second to reach a face marks the partner cell of
+    // the holder and its own.  Then every other stream tetrahedron looks its
+    // faces up and marks the holder's cell.  A mark that finds its cell set
+    // means a third tetrahedron on one face: exhaustive pairing instead.
     if (mask & kRelTT) {
+        using CL = Cells<kL>;
+        using CT = typename CL::T;
+        CT *win = reinterpret_cast<CT *>(base + pl.win);
+        CT *ht = reinterpret_cast<CT *>(base + pl.ht);
+        uint32_t *win32 = reinterpret_cast<uint32_t *>(win);
+        uint32_t *ht32 = reinterpret_cast<uint32_t *>(ht);
+        const int H = pl.H;
         const int cap = it.cap_tt;
-        const bool room = cap >= 4 * nT;  // the host always sizes TT for at least 4 per row
-        for (int p = tid; p < ns && room; p += B) {
-            if (!internal(p)) continue;
-            const int row = ibp[p >> 6] + __popcll(ib[p >> 6] & ((1ull << (p & 63)) - 1ull));
-            int q0 = -1, q1 = -1, q2 = -1, q3 = -1;
-            int raw = 0;
-            {
-                const int4 t = tet(p);
-                // Faces omitting t.z or t.w both hold the edge (t.x, t.y); faces
-                // omitting t.x or t.y both hold (t.z, t.w).  The tetrahedra
-                // around an edge are the entries of one endpoint's list that hold
-                // the other endpoint: scan the shorter list of each edge, keep
-                // those, and sort them to faces by the remaining two vertices.
-                const int sx = cnt[t.x], ex = cnt[t.x + 1], sy = cnt[t.y], ey = cnt[t.y + 1];
-                const int sz = cnt[t.z], ez = cnt[t.z + 1], sw = cnt[t.w], ew = cnt[t.w + 1];
-                // branch-free selects keep the four slots in registers
-                auto record = [&](int q) {
-                    q0 = raw == 0 ? q : q0;
-                    q1 = raw == 1 ? q : q1;
-                    q2 = raw == 2 ? q : q2;
-                    q3 = raw == 3 ? q : q3;
-                    ++raw;
-                };
-                auto edge = [&](int st, int en, int other, int f0, int f1) {
-                    auto visit = [&](int q, int4 tq) {
-                        if (q != p && has_vertex(tq, other)) {
-                            if (has_vertex(tq, f0)) record(q);
-                            if (has_vertex(tq, f1)) record(q);
-                        }
-                    };
-                    int i = st;
-                    for (; i + 4 <= en; i += 4) {
-                        const int qa = lvt[i], qb = lvt[i + 1], qc = lvt[i + 2], qd = lvt[i + 3];
-                        const int4 ta = tet(qa), tb2 = tet(qb), tc = tet(qc), td = tet(qd);
-                        visit(qa, ta);
-                        visit(qb, tb2);
-                        visit(qc, tc);
-                        visit(qd, td);
-                    }
-                    for (; i < en; ++i) {
-                        const int q = lvt[i];
-                        visit(q, tet(q));
-                    }
-                };
-                if (ex - sx <= ey - sy) edge(sx, ex, t.y, t.z, t.w);
-                else edge(sy, ey, t.x, t.z, t.w);
-                if (ez - sz <= ew - sw) edge(sz, ez, t.w, t.x, t.y);
-                else edge(sw, ew, t.z, t.x, t.y);
-                if (raw > 4) s_fail = 1;  // a face shared by three or more tetrahedra: exhaustive path
+        const int win_words = kL ? 2 * nT : 4 * nT;  // 4 cells per row
+        const int ht_words = kL ? H / 2 : H;
+
+        // Walk the chain of face {fa < fb < fc} (linear probing).  kIns: enter
+        // it (internal tetrahedron me, its face kme) or only look it up.
+        auto visit = [&](auto ins_tag, uint32_t h, int fa, int fb, int fc, int me, int kme) {
+            constexpr bool kIns = decltype(ins_tag)::value;
+            uint32_t idx = (uint32_t)(((unsigned long long)h * (uint32_t)H) >> 32);
+            int left = H + 2;  // a failed swap re-reads its cell; each cell changes once
+            bool active = true;
+            while (active) {
+                uint32_t w;
+                const uint32_t c = CL::read(ht, idx, w);
+                const int q = c == 0u ? 0 : (int)c - 1;
+                // the holder's face that is {fa, fb, fc}, if any (a tetrahedron
+                // meets its own earlier faces on the way: skip them)
+                const int kq = face_index(tet(q), fa, fb, fc);
+                const bool hit = c != 0u && q != me && kq >= 0;
+                bool stop = hit || (c == 0u && !kIns);
+                if (kIns && c == 0u) stop = CL::try_set(ht, idx, w, (uint32_t)me + 1u);
+                if (hit) {
+                    bool bad = CL::mark(win, 4 * (uint32_t)q + kq, (uint32_t)me + 1u);
+                    if (kIns) bad |= CL::mark(win, 4 * (uint32_t)me + kme, c);
+                    if (bad) s_fail = 1;
+                }
+                if (c != 0u && !hit) idx = idx + 1 == (uint32_t)H ? 0u : idx + 1;
+                if (--left == 0 && !stop) {
+                    if (kIns) s_full = 1;
+                    stop = true;
+                }
+                active = !stop;
             }
-            int n0 = q0 >= 0 ? idg[q0] & kIdMask : 0x7fffffff;
-            int n1 = q1 >= 0 ? idg[q1] & kIdMask : 0x7fffffff;
-            int n2 = q2 >= 0 ? idg[q2] & kIdMask : 0x7fffffff;
-            int n3 = q3 >= 0 ? idg[q3] & kIdMask : 0x7fffffff;
-            cswap(n0, n1); cswap(n2, n3); cswap(n0, n2); cswap(n1, n3); cswap(n1, n2);
-            // a duplicated tetrahedron is reached through several faces: list it once
-            if (n3 == n2) n3 = 0x7fffffff;
-            if (n2 == n1) { n2 = n3; n3 = 0x7fffffff; }
-            if (n1 == n0) { n1 = n2; n2 = n3; n3 = 0x7fffffff; }
-            const int c = (n0 != 0x7fffffff) + (n1 != 0x7fffffff) + (n2 != 0x7fffffff) + (n3 != 0x7fffffff);
-            if (row < nT && room) {
-                blk[lay.trows + row] = idg[p] & kIdMask;
-                blk[lay.tt_off + row] = c;
-                int32_t *w = blk + lay.tt_ent + 4 * (int64_t)row;
-                if (c > 0) w[0] = n0;
-                if (c > 1) w[1] = n1;
-                if (c > 2) w[2] = n2;
-                if (c > 3) w[3] = n3;
+        };
+        auto faces = [&](auto ins_tag, int4 s, int pass, int P, int me) {
+#pragma unroll 1
+            for (int k = 0; k < 4; ++k) {
+                int fa, fb, fc;
+                face_of(s, k, fa, fb, fc);
+                const uint32_t h = face_hash(fa, fb, fc);
+                if (P == 1 || (int)(((h & 0xFFFFu) * (uint32_t)P) >> 16) == pass)
+                    visit(ins_tag, h, fa, fb, fc, me, k);
+            }
+        };
+        using Ins = std::integral_constant<bool, true>;
+        using Look = std::integral_constant<bool, false>;
+
+        int P = pl.P;
+        while (true) {
+            for (int i = tid; i < win_words; i += B) win32[i] = 0u;
+            for (int pass = 0; pass < P; ++pass) {
+                for (int i = tid; i < ht_words; i += B) ht32[i] = 0u;
+                __syncthreads();
+                for (int p = tid; p < nT; p += B) faces(Ins{}, tet(p), pass, P, p);
+                __syncthreads();
+                PHASE_MARK(7);
+                if (s_full) break;
+                for (int p = nT + tid; p < ntot; p += B) faces(Look{}, tet_global(p), pass, P, p);
+                __syncthreads();
+                PHASE_MARK(8);
+            }
+            const int full = s_full, fail = s_fail;
+            __syncthreads();
+            if (!full || fail) break;
+            // a pass overfilled the table: twice the passes, from the start
+            P *= 2;
+            if (tid == 0) s_full = 0;
+            if (P > kMaxFacePasses) {
+                if (tid == 0) s_fail = 1;
+                break;
             }
         }
         __syncthreads();
-        int rcarry = nT, ecarry = 0;
-        const bool exhaustive = s_fail || !room;
-        if (!exhaustive) {
+        PHASE_MARK(1);
+        int ecarry = 0;
+        if (s_fail == 0) {
+            // partners mapped to original ids, sorted; a repeated tetrahedron
+            // reached through several faces is listed once
             for (int r0 = 0; r0 < nT; r0 += B) {
                 const int r = r0 + tid;
-                int c = 0, e0 = 0, e1 = 0, e2 = 0, e3 = 0;
+                int n0 = 0x7fffffff, n1 = 0x7fffffff, n2 = 0x7fffffff, n3 = 0x7fffffff;
+                int c = 0;
                 if (r < nT) {
-                    c = blk[lay.tt_off + r];
-                    const int32_t *w = blk + lay.tt_ent + 4 * (int64_t)r;
-                    if (c > 0) e0 = w[0];
-                    if (c > 1) e1 = w[1];
-                    if (c > 2) e2 = w[2];
-                    if (c > 3) e3 = w[3];
+                    const uint32_t w0 = CL::get(win, 4 * r), w1 = CL::get(win, 4 * r + 1);
+                    const uint32_t w2 = CL::get(win, 4 * r + 2), w3 = CL::get(win, 4 * r + 3);
+                    if (w0 != 0u) n0 = idg[w0 - 1] & kIdMask;
+                    if (w1 != 0u) n1 = idg[w1 - 1] & kIdMask;
+                    if (w2 != 0u) n2 = idg[w2 - 1] & kIdMask;
+                    if (w3 != 0u) n3 = idg[w3 - 1] & kIdMask;
+                    cswap(n0, n1); cswap(n2, n3); cswap(n0, n2); cswap(n1, n3); cswap(n1, n2);
+                    if (n3 == n2) n3 = 0x7fffffff;
+                    if (n2 == n1) { n2 = n3; n3 = 0x7fffffff; }
+                    if (n1 == n0) { n1 = n2; n2 = n3; n3 = 0x7fffffff; }
+                    c = (n0 != 0x7fffffff) + (n1 != 0x7fffffff) + (n2 != 0x7fffffff) + (n3 != 0x7fffffff);
                 }
                 int tot;
-                const int ex = block_excl_scan<B>(c, tot);  // its barriers order every read before the writes
+                const int ex = block_excl_scan<B>(c, tot, sp);
                 if (r < nT) {
+                    const int32_t id = idg[r];
+                    if (id >= 0) s_status |= kStInconsistent;  // position r must be internal
                     const int o = ecarry + ex;
+                    blk[lay.trows + r] = id & kIdMask;
                     blk[lay.tt_off + r] = o;
-                    int32_t *w = blk + lay.tt_ent + o;
-                    if (c > 0) w[0] = e0;
-                    if (c > 1) w[1] = e1;
-                    if (c > 2) w[2] = e2;
-                    if (c > 3) w[3] = e3;
+                    if (o + c <= cap) {
+                        int32_t *w = blk + lay.tt_ent + o;
+                        if (c > 0) w[0] = n0;
+                        if (c > 1) w[1] = n1;
+                        if (c > 2) w[2] = n2;
+                        if (c > 3) w[3] = n3;
+                    }
                 }
                 ecarry += tot;
             }
-        }
-        __syncthreads();
-        PHASE_MARK(8);
-        if (exhaustive) {
-            // exhaustive pairing, rows rebuilt from scratch (non-manifold faces)
+        } else {
+            // exhaustive pairing (non-manifold faces); rows are positions 0..nT-1
             if (tid == 0) s_status |= kStTTFallback;
-            rcarry = 0;
-            ecarry = 0;
-            for (int p0 = 0; p0 < ns; p0 += B) {
-                const int p = p0 + tid;
-                const bool in = internal(p);
+            auto tet_any = [&](int q) -> int4 { return q < nT ? tet(q) : tet_global(q); };
+            for (int r0 = 0; r0 < nT; r0 += B) {
+                const int r = r0 + tid;
                 int c = 0;
                 int4 t = make_int4(0, 0, 0, 0);
-                if (in) {
-                    t = tet(p);
+                if (r < nT) {
+                    t = tet(r);
                     for (int q = 0; q < ntot; ++q)
-                        if (q != p && shared_vertices(t, tet(q)) >= 3) ++c;
+                        if (q != r && shared_vertices(t, tet_any(q)) >= 3) ++c;
                 }
-                int rtot, etot;
-                const int rex = block_excl_scan<B>(in ? 1 : 0, rtot);
-                const int eex = block_excl_scan<B>(c, etot);
-                if (in) {
-                    const int row = rcarry + rex;
+                int etot;
+                const int eex = block_excl_scan<B>(c, etot, sp);
+                if (r < nT) {
                     int pos = ecarry + eex;
-                    if (row < nT) {
-                        blk[lay.trows + row] = idg[p] & kIdMask;
-                        blk[lay.tt_off + row] = pos;
-                    }
+                    blk[lay.trows + r] = idg[r] & kIdMask;
+                    blk[lay.tt_off + r] = pos;
                     const int start = pos;
                     for (int q = 0; q < ntot; ++q) {
-                        if (q != p && shared_vertices(t, tet(q)) >= 3) {
+                        if (q != r && shared_vertices(t, tet_any(q)) >= 3) {
                             if (pos < cap) blk[lay.tt_ent + pos] = idg[q] & kIdMask;
                             ++pos;
                         }
                     }
-                    // the star part and the halo part are each ascending; sort the row
                     const int end = min(pos, cap);
                     for (int i = start + 1; i < end; ++i) {
                         const int32_t x = blk[lay.tt_ent + i];
@@ -658,17 +492,246 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
                         blk[lay.tt_ent + j + 1] = x;
                     }
                 }
-                rcarry += rtot;
                 ecarry += etot;
             }
         }
         if (tid == 0) {
-            blk[lay.tt_off + (rcarry <= nT ? rcarry : nT)] = ecarry;
+            blk[lay.tt_off + nT] = ecarry;
             blk[5] = ecarry;
-            if (rcarry != nT) s_status |= kStInconsistent;
             if (ecarry > cap) s_status |= kStTTOverflow;
         }
-        PHASE_MARK(9);
+        __syncthreads();
+        PHASE_MARK(2);
+        if (want_v) {
+            stage(nT, ns);
+            __syncthreads();
+        }
+    }
+
+    if (want_v) {
+        LidT *rix = reinterpret_cast<LidT *>(base + pl.rix);
+        LidT *rowl = reinterpret_cast<LidT *>(base + pl.rowl);
+        int32_t *cnt = reinterpret_cast<int32_t *>(base + pl.cnt);
+        PosT *lvt = reinterpret_cast<PosT *>(base + pl.lvt);
+        uint32_t *wbm = reinterpret_cast<uint32_t *>(base + pl.wbm);
+        constexpr LidT kNoRow = (LidT)-1;
+
+        // rows: row index of each local vertex, local id of each row, row ids
+        {
+            int carry = 0;
+            for (int i0 = 0; i0 < L; i0 += B) {
+                const int i = i0 + tid;
+                const int32_t lv = i < L ? lvg[i] : 0;
+                const int f = (i < L && lv < 0) ? 1 : 0;
+                int tot;
+                const int ex = block_excl_scan<B>(f, tot, sp);
+                if (i < L) {
+                    const int r = carry + ex;
+                    const bool row = f && r < nV;
+                    rix[i] = row ? (LidT)r : kNoRow;
+                    if (row) {
+                        rowl[r] = (LidT)i;
+                        blk[lay.vrows + r] = lv & kIdMask;
+                    }
+                }
+                carry += tot;
+            }
+            if (tid == 0 && carry != nV) s_status |= kStInconsistent;
+        }
+        for (int r = tid; r <= nV; r += B) cnt[r] = 0;
+        __syncthreads();
+
+        // ---- local VT of the rows (the star holds every tetrahedron of a row)
+        for (int p = tid; p < ns; p += B) {
+            const int4 t = tet(p);
+            const LidT r0 = rix[t.x], r1 = rix[t.y], r2 = rix[t.z], r3 = rix[t.w];
+            if (r0 != kNoRow) atomicAdd(&cnt[r0], 1);
+            if (r1 != kNoRow) atomicAdd(&cnt[r1], 1);
+            if (r2 != kNoRow) atomicAdd(&cnt[r2], 1);
+            if (r3 != kNoRow) atomicAdd(&cnt[r3], 1);
+        }
+        __syncthreads();
+        {
+            int carry = 0;
+            for (int r0 = 0; r0 < nV; r0 += B) {
+                const int r = r0 + tid;
+                const int x = r < nV ? cnt[r] : 0;
+                int tot;
+                const int ex = block_excl_scan<B>(x, tot, sp);
+                if (r < nV) cnt[r] = carry + ex + x;  // end of the list
+                carry += tot;
+            }
+            if (tid == 0) {
+                cnt[nV] = carry;
+                if (carry != m.nnzVT) s_status |= kStInconsistent;
+            }
+        }
+        __syncthreads();
+        const bool vt_ok = cnt[nV] == m.nnzVT;  // else the lists would not fit
+        if (vt_ok) {
+            for (int p = tid; p < ns; p += B) {
+                const int4 t = tet(p);
+                const LidT r0 = rix[t.x], r1 = rix[t.y], r2 = rix[t.z], r3 = rix[t.w];
+                if (r0 != kNoRow) lvt[atomicSub(&cnt[r0], 1) - 1] = (PosT)p;
+                if (r1 != kNoRow) lvt[atomicSub(&cnt[r1], 1) - 1] = (PosT)p;
+                if (r2 != kNoRow) lvt[atomicSub(&cnt[r2], 1) - 1] = (PosT)p;
+                if (r3 != kNoRow) lvt[atomicSub(&cnt[r3], 1) - 1] = (PosT)p;
+            }
+        }
+        __syncthreads();  // cnt[r] = start of row r's list, cnt[r+1] = its end
+        PHASE_MARK(3);
+        // ---- VT: a row's tetrahedra by original id; the offsets are the lists'
+        if ((mask & kRelVT) && vt_ok) {
+            for (int r = tid; r < nV; r += B) {
+                const int s0 = cnt[r], n = cnt[r + 1] - s0;
+                blk[lay.vt_off + r] = s0;
+                int32_t *dst = blk + lay.vt_ent + s0;
+                if (n <= 32) {
+                    uint32_t v[32];
+#pragma unroll
+                    for (int i = 0; i < 32; ++i)
+                        v[i] = i < n ? (uint32_t)(idg[lvt[s0 + i]] & kIdMask) : 0xFFFFFFFFu;
+                    sort32(v);
+#pragma unroll
+                    for (int i = 0; i < 32; ++i)
+                        if (i < n) dst[i] = (int32_t)v[i];
+                } else {
+                    // long rows (high valence): insertion sort in place
+                    for (int i = 0; i < n; ++i) {
+                        const int32_t x = idg[lvt[s0 + i]] & kIdMask;
+                        int j = i - 1;
+                        while (j >= 0 && dst[j] > x) {
+                            dst[j + 1] = dst[j];
+                            --j;
+                        }
+                        dst[j + 1] = x;
+                    }
+                }
+            }
+            if (tid == 0) blk[lay.vt_off + nV] = cnt[nV];
+            __syncthreads();
+            PHASE_MARK(4);
+        }
+
+        // ---- VV: one row at a time per group of 32 lanes.  Marking the row's
+        // neighbours in the group's bitmap over the local table removes
+        // repeats: the lane that sets a bit stages that vertex.  A staged
+        // vertex's place in the row is the number of staged vertices below it
+        // (local ids are in original id order).  Rows with more neighbours than
+        // the stage holds read them from the bitmap in word order instead.
+        if ((mask & kRelVV) && vt_ok) {
+            constexpr int G = 32;
+            constexpr int NG = B / G;
+            __shared__ int s_gcnt[NG];
+            const int W = pl.W;
+            const int grp = tid / G, gl = tid % G;
+            uint32_t *wb = wbm + (int64_t)grp * W;
+            LidT *stg = reinterpret_cast<LidT *>(base + pl.stg) + (int64_t)grp * kVVStage;
+            const int cap = it.cap_vv;
+            for (int w = gl; w < W; w += G) wb[w] = 0u;
+            if (gl == 0) s_gcnt[grp] = 0;
+            wave_fence();
+            auto mark = [&](int v, int self) {
+                if (v != self) {
+                    const uint32_t bit = 1u << (v & 31);
+                    if ((atomicOr(&wb[v >> 5], bit) & bit) == 0u) {
+                        const int k = atomicAdd(&s_gcnt[grp], 1);
+                        if (k < kVVStage) stg[k] = (LidT)v;
+                    }
+                }
+            };
+            // the distinct neighbours of row r; returns their count
+            auto gather = [&](int r) -> int {
+                const int self = rowl[r];
+                for (int i = cnt[r] + gl; i < cnt[r + 1]; i += G) {
+                    const int4 t = tet(lvt[i]);
+                    mark(t.x, self);
+                    mark(t.y, self);
+                    mark(t.z, self);
+                    mark(t.w, self);
+                }
+                wave_fence();
+                return s_gcnt[grp];
+            };
+            // clear what the row set: the staged vertices' words, or everything
+            auto clear = [&](int c) {
+                if (c <= kVVStage) {
+                    for (int k = gl; k < c; k += G) wb[stg[k] >> 5] = 0u;
+                } else {
+                    for (int w = gl; w < W; w += G) wb[w] = 0u;
+                }
+                wave_fence();
+                if (gl == 0) s_gcnt[grp] = 0;
+                wave_fence();
+            };
+            // pass 1: counts
+            for (int r = grp; r < nV; r += NG) {
+                const int c = gather(r);
+                if (gl == 0) blk[lay.vv_off + r] = c;  // the count, turned into the offset below
+                clear(c);
+            }
+            __syncthreads();
+            PHASE_MARK(5);
+            int carry = 0;
+            for (int r0 = 0; r0 < nV; r0 += B) {
+                const int r = r0 + tid;
+                const int x = r < nV ? blk[lay.vv_off + r] : 0;
+                int tot;
+                const int ex = block_excl_scan<B>(x, tot, sp);
+                if (r < nV) blk[lay.vv_off + r] = carry + ex;
+                carry += tot;
+            }
+            if (tid == 0) {
+                blk[lay.vv_off + nV] = carry;
+                blk[4] = carry;
+                if (carry > cap) s_status |= kStVVOverflow;
+            }
+            __syncthreads();
+            // pass 2: entries
+            if (carry <= cap) {
+                for (int r = grp; r < nV; r += NG) {
+                    const int c = gather(r);
+                    int32_t *dst = blk + lay.vv_ent + blk[lay.vv_off + r];
+                    if (c <= kVVStage) {
+                        const int v0 = gl < c ? (int)stg[gl] : 0x7fffffff;
+                        const int v1 = gl + G < c ? (int)stg[gl + G] : 0x7fffffff;
+                        int k0 = 0, k1 = 0;
+                        for (int j = 0; j < c; ++j) {
+                            const int x = stg[j];
+                            k0 += x < v0;
+                            k1 += x < v1;
+                        }
+                        if (gl < c) dst[k0] = lvg[v0] & kIdMask;
+                        if (gl + G < c) dst[k1] = lvg[v1] & kIdMask;
+                    } else {
+                        // many neighbours: the bitmap in word order
+                        int o = 0;
+                        for (int w0 = 0; w0 < W; w0 += G) {
+                            const int w = w0 + gl;
+                            uint32_t bits = w < W ? wb[w] : 0u;
+                            const int n = __popc(bits);
+                            int x = n;
+                            #pragma unroll
+                            for (int d = 1; d < G; d <<= 1) {
+                                const int y = __shfl_up(x, d, G);
+                                if (gl >= d) x += y;
+                            }
+                            const int tot = __shfl(x, G - 1, G);
+                            int pos = o + x - n;
+                            while (bits) {
+                                const int b = __ffs(bits) - 1;
+                                bits &= bits - 1u;
+                                dst[pos++] = lvg[w * 32 + b] & kIdMask;
+                            }
+                            o += tot;
+                        }
+                    }
+                    clear(c);
+                }
+            }
+            __syncthreads();
+            PHASE_MARK(6);
+        }
     }
     __syncthreads();
 

@@ -9,13 +9,16 @@
 //                                ascending original id; bit 31 set when the
 //                                vertex belongs to C (a VT/VV row).
 //   tets (bytes from tb_off)     the four local vertex ids of each stream
-//                                tetrahedron, as 4 x uint16 (8 B) when the
-//                                local table has at most 65535 vertices, else
-//                                as 4 x int32 (16 B, flag bit 0); first the ns tetrahedra of
-//                                star(C) (at least one vertex in C) in ascending
-//                                original id, then the nh halo tetrahedra
-//                                (no vertex in C, sharing a triangle with a
-//                                tetrahedron internal to C), ascending.
+//                                tetrahedron, ascending, as 4 x uint16 (8 B)
+//                                when the local table has at most 65535
+//                                vertices, else as 4 x int32 (16 B, flag bit
+//                                0).  Order: first the nT tetrahedra internal
+//                                to C (stream position = TT row), then the
+//                                rest of star(C) (at least one vertex in C),
+//                                then the nh halo tetrahedra (no vertex in C,
+//                                sharing a triangle with a tetrahedron
+//                                internal to C); each part in ascending
+//                                original id.  ns counts the whole star.
 //   tid[tet_off .. +ns+nh)       original tetrahedron id; bit 31 set when the
 //                                tetrahedron is internal to C (a TT row).
 //
@@ -131,22 +134,69 @@ GALE_HD BlockLayout block_layout(uint32_t mask, int32_t nV, int32_t nT, int32_t 
 // Where each working array lives, as byte offsets from the base of the LDS
 // (LDS path) or of the workgroup's global workspace slice (global path).
 //   lt    stream tetrahedra, 4 x uint16 local ids           (LDS path only)
-//   ib    internal flag of each star tetrahedron, 1 bit
-//   ibp   internal tetrahedra before each 64-bit word of ib (TT row index)
-//   cnt   local VT offsets, one per local vertex + 1
-//   lvt   local VT entries: stream positions, 4 per stream tetrahedron
-//   rowl  local id of each row (vertex of the cluster)
-//   wbm   one bitmap over the local vertex table per row group (VV; 32 groups)
+//         (only the internal ones while TT runs; the rest is staged after)
+// TT uses the region after the internal tetrahedra for
+//   win   four partner cells per TT row (stream positions, one per face)
+//   ht    face table: H cells holding the stream position of a tetrahedron
+// cells are uint16 in LDS and int32 in the global workspace.  VT / VV use
+// the region after the star tetrahedra (in the workspace: from its start) for
+//   rix   row index of each local vertex (all ones: not a vertex of the cluster)
+//   rowl  local id of each row
+//   cnt   local VT offsets of the rows, nV + 1
+//   lvt   local VT entries: stream positions, nnzVT
+//   wbm   one bitmap over the local vertex table per row group (VV)
+//   stg   the distinct neighbours of the row a group works on (VV)
 struct Plan {
     int32_t ok;       // LDS path possible within the budget
     int32_t W;        // bitmap words per row
-    int64_t lt, ib, ibp, cnt, lvt, rowl, wbm;
+    int32_t H;        // face table cells
+    int32_t P;        // face table passes (faces split by hash)
+    int64_t lt, win, ht, rix, rowl, cnt, lvt, wbm, stg;
     int64_t bytes;
 };
 
 GALE_HD int64_t align16(int64_t b) { return (b + 15) / 16 * 16; }
 
-// LDS path: uint16 local ids and stream positions.  Offsets are assigned on
+constexpr int kMaxFacePasses = 16;
+constexpr int kVVStage = 64;  // distinct neighbours of a VV row staged per row group
+
+// Face table passes for H cells: distinct faces are estimated at 2.5 per TT
+// row (a closed region has 2 plus half its boundary) at load 0.7; the kernel
+// doubles the count and starts again if a pass fills the table.
+GALE_HD int32_t face_passes(int32_t nT, int64_t H) {
+    if (H <= 0) return 0;
+    const int64_t est = (5 * (int64_t)nT) / 2 + 64;
+    const int64_t per = (7 * H) / 10 > 0 ? (7 * H) / 10 : 1;
+    const int64_t P = (est + per - 1) / per;
+    return (int32_t)(P < 1 ? 1 : P);
+}
+
+// Face table cells kept per TT row at most (load about 1/3 on a closed region).
+GALE_HD int64_t face_cells_max(int32_t nT) { return 6 * (int64_t)nT + 64; }
+
+// VT / VV arrays from byte offset off (cell: bytes of an id or position);
+// returns the end.
+GALE_HD int64_t v_arrays(Plan &p, const ClusterMeta &m, uint32_t mask, int64_t off, int cell) {
+    const bool v = (mask & (kRelVT | kRelVV)) != 0;
+    const bool vv = (mask & kRelVV) != 0;
+    const int64_t ngroups = 32;
+    p.W = (m.L + 31) / 32;
+    p.rix = off;
+    off += v ? align16((int64_t)m.L * cell) : 0;
+    p.rowl = off;
+    off += v ? align16((int64_t)m.nV * cell) : 0;
+    p.cnt = off;
+    off += v ? align16(((int64_t)m.nV + 1) * 4) : 0;
+    p.lvt = off;
+    off += v ? align16((int64_t)m.nnzVT * cell) : 0;
+    p.wbm = off;
+    off += vv ? align16(ngroups * (int64_t)p.W * 4) : 0;
+    p.stg = off;
+    off += vv ? align16(ngroups * (int64_t)kVVStage * cell) : 0;
+    return off;
+}
+
+// LDS path: uint16 local ids, positions and cells.  Offsets are assigned on
 // every path with no early return (the same offsets for every mask).
 GALE_HD Plan lds_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32_t block_threads) {
     Plan p{};
@@ -154,57 +204,44 @@ GALE_HD Plan lds_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32
     const bool narrow = m.L <= 65535 && ntot <= 65535;
     const bool tt = (mask & kRelTT) != 0;
     const bool v = (mask & (kRelVT | kRelVV)) != 0;
-    const bool vv = (mask & kRelVV) != 0;
-    const int64_t ngroups = 32;
     (void)block_threads;
-    p.W = (m.L + 31) / 32;
-    int64_t off = 0;
-    p.lt = off;
-    off += align16(ntot * 8);
-    p.ib = off;
-    off += tt ? align16((int64_t)((m.ns + 63) / 64) * 8) : 0;
-    p.ibp = off;
-    off += tt ? align16((int64_t)((m.ns + 63) / 64) * 4) : 0;
-    p.cnt = off;
-    off += align16(((int64_t)m.L + 1) * 4);
-    p.lvt = off;
-    off += align16(ntot * 4 * 2);
-    p.rowl = off;
-    off += v ? align16((int64_t)m.nV * 2) : 0;
-    p.wbm = off;
-    off += vv ? align16(ngroups * (int64_t)p.W * 4) : 0;
-    p.bytes = off;
-    p.ok = (narrow && off <= budget) ? 1 : 0;
+    p.lt = 0;
+    // TT: partner cells, then the table takes what is left (an even count)
+    p.win = align16((int64_t)m.nT * 8);
+    p.ht = p.win + (tt ? align16((int64_t)m.nT * 4 * 2) : 0);
+    int64_t h = tt ? (budget - p.ht) / 2 : 0;
+    const int64_t hmax = face_cells_max(m.nT);
+    h = h > hmax ? hmax : h;
+    h = h < 0 ? 0 : h & ~(int64_t)1;
+    p.H = (int32_t)h;
+    p.P = tt ? face_passes(m.nT, h) : 0;
+    const int64_t tt_end = p.ht + 2 * h;
+    // VT / VV after the star tetrahedra (the halo holds no vertex of C)
+    const int64_t v_end = v_arrays(p, m, mask, align16((int64_t)m.ns * 8), 2);
+    p.bytes = tt_end > v_end ? tt_end : v_end;
+    const bool tt_ok = !tt || (h >= 64 && p.P <= kMaxFacePasses / 2 && tt_end <= budget);
+    const bool v_ok = !v || v_end <= budget;
+    p.ok = (narrow && tt_ok && v_ok) ? 1 : 0;
     return p;
 }
 
-// Global path: the same arrays (minus the staged stream and flag bits) in the
-// workgroup's workspace slice, with 32-bit entries.
+// Global path: the same arrays in the workgroup's workspace slice with 32-bit
+// ids, positions and cells; the stream is read from global memory.  TT and
+// VT / VV both start at the slice base (TT is finished first).
 GALE_HD Plan ws_plan(const ClusterMeta &m, uint32_t mask, int32_t block_threads) {
     Plan p{};
-    const int64_t ntot = (int64_t)m.ns + m.nh;
-    const bool v = (mask & (kRelVT | kRelVV)) != 0;
-    const bool vv = (mask & kRelVV) != 0;
-    const int64_t ngroups = 32;
+    const bool tt = (mask & kRelTT) != 0;
     (void)block_threads;
     p.ok = 1;
-    p.W = (m.L + 31) / 32;
-    int64_t off = 0;
-    const bool tt = (mask & kRelTT) != 0;
     p.lt = 0;
-    p.ib = off;
-    off += tt ? align16((int64_t)((m.ns + 63) / 64) * 8) : 0;
-    p.ibp = off;
-    off += tt ? align16((int64_t)((m.ns + 63) / 64) * 4) : 0;
-    p.cnt = off;
-    off += align16(((int64_t)m.L + 1) * 4);
-    p.lvt = off;
-    off += align16(ntot * 4 * 4);
-    p.rowl = off;
-    off += v ? align16((int64_t)m.nV * 4) : 0;
-    p.wbm = off;
-    off += vv ? align16(ngroups * (int64_t)p.W * 4) : 0;
-    p.bytes = off;
+    p.win = 0;
+    p.ht = tt ? align16((int64_t)m.nT * 4 * 4) : 0;
+    const int64_t h = tt ? face_cells_max(m.nT) : 0;
+    p.H = (int32_t)h;
+    p.P = tt ? 1 : 0;
+    const int64_t tt_end = p.ht + 4 * h;
+    const int64_t v_end = v_arrays(p, m, mask, 0, 4);
+    p.bytes = tt_end > v_end ? tt_end : v_end;
     return p;
 }
 

@@ -14,7 +14,9 @@
 //      intersecting the (ascending) global VT lists of the triangle's vertices
 //      and appended as the halo, so that TT rows are complete;
 //   5. local vertex table = sorted distinct vertices of star, halo and C;
-//      stream tetrahedra are re-expressed in local ids.
+//      stream tetrahedra are re-expressed in local ids, each tetrahedron's
+//      four ids ascending, in the order: internal tetrahedra (the TT rows),
+//      the rest of star(C), the halo, each part in ascending tetrahedron id.
 // Everything here is integer bookkeeping; no relation entry is produced.
 #include <algorithm>
 #include <atomic>
@@ -365,21 +367,29 @@ gale_status prepare_streams(int32_t nv, int64_t nt, const int32_t *tv, const int
                     const bool wide = (m.flags & kMetaWide) != 0;
                     uint8_t *tb = out.tets.data() + m.tb_off;
                     auto put = [&](int64_t i, int32_t t) {
+                        int32_t l[4];
+                        for (int j = 0; j < 4; ++j) l[j] = local(tv[4 * (int64_t)t + j]);
+                        std::sort(l, l + 4);
                         for (int j = 0; j < 4; ++j) {
-                            const int32_t l = local(tv[4 * (int64_t)t + j]);
                             if (wide) {
-                                std::memcpy(tb + 16 * i + 4 * j, &l, 4);
+                                std::memcpy(tb + 16 * i + 4 * j, &l[j], 4);
                             } else {
-                                const uint16_t l16 = (uint16_t)l;
+                                const uint16_t l16 = (uint16_t)l[j];
                                 std::memcpy(tb + 8 * i + 2 * j, &l16, 2);
                             }
                         }
                     };
                     int64_t p = m.tet_off, i = 0;
-                    for (int64_t s = soff[k]; s < soff[k + 1]; ++s, ++p, ++i) {
-                        const int32_t t = star[s];
-                        put(i, t);
-                        out.tid[p] = owner[t] == k ? (int32_t)((uint32_t)t | 0x80000000u) : t;
+                    for (int pass = 0; pass < 2; ++pass) {  // internal first, then the rest of the star
+                        for (int64_t s = soff[k]; s < soff[k + 1]; ++s) {
+                            const int32_t t = star[s];
+                            const bool in = owner[t] == k;
+                            if (in != (pass == 0)) continue;
+                            put(i, t);
+                            out.tid[p] = in ? (int32_t)((uint32_t)t | 0x80000000u) : t;
+                            ++p;
+                            ++i;
+                        }
                     }
                     for (int64_t s = hoff[k]; s < hoff[k + 1]; ++s, ++p, ++i) {
                         const int32_t t = halo[s].second;

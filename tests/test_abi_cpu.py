@@ -72,6 +72,19 @@ def test_create_without_device_is_edevice():
 
 
 def test_binding_refuses_missing_library(tmp_path):
-    from paper_2507_15230_amd import gale
-    with pytest.raises(RuntimeError):
-        gale.load_library(str(tmp_path / "missing.so")) if gale._lib is None else (_ for _ in ()).throw(RuntimeError())
+    """In a fresh interpreter (nothing loaded yet) the binding raises when the
+    library file is absent: there is no fallback path."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_2507_15230_amd import gale\n"
+        "try:\n"
+        "    gale.load_library(%r)\n"
+        "except RuntimeError as e:\n"
+        "    print('refused', e)\n"
+        "    sys.exit(0)\n"
+        "sys.exit(3)\n" % (ROOT, str(tmp_path / "missing.so")))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "refused" in r.stdout
