@@ -530,7 +530,12 @@ gale_status gale_create(const gale_config *cfg_in, gale_ctx **out) {
     ctx->num_cus = prop.multiProcessorCount;
     ctx->block_threads = cfg.block_threads ? cfg.block_threads : 1024;
     // LDS: the device limit minus what the kernels declare statically
-    const int64_t static_lds = 512;
+    int64_t static_lds = 0;
+    e = static_lds_bytes(&static_lds);
+    if (e != hipSuccess) {
+        delete ctx;
+        return fail(GALE_EDEVICE, std::string("kernel attributes: ") + hipGetErrorString(e));
+    }
     int64_t budget = (int64_t)prop.sharedMemPerBlock - static_lds;
     if (cfg.lds_bytes > 0) budget = std::min<int64_t>(budget, cfg.lds_bytes);
     ctx->lds_budget = std::max<int64_t>(budget, 0);

@@ -416,6 +416,14 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
         }
         __syncthreads();
         PHASE_MARK(1);
+        // tetrahedron ids: from a copy over the face table when it fits (LDS path)
+        int32_t *idl = reinterpret_cast<int32_t *>(ht);
+        const bool ids_lds = kL && 2 * (int64_t)H >= 4 * (int64_t)ntot;
+        if (ids_lds) {
+            for (int i = tid; i < ntot; i += B) idl[i] = idg[i];
+            __syncthreads();
+        }
+        auto id_of = [&](int p) -> int32_t { return ids_lds ? idl[p] : idg[p]; };
         int ecarry = 0;
         if (s_fail == 0) {
             // partners mapped to original ids, sorted; a repeated tetrahedron
@@ -427,10 +435,10 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
                 if (r < nT) {
                     const uint32_t w0 = CL::get(win, 4 * r), w1 = CL::get(win, 4 * r + 1);
                     const uint32_t w2 = CL::get(win, 4 * r + 2), w3 = CL::get(win, 4 * r + 3);
-                    if (w0 != 0u) n0 = idg[w0 - 1] & kIdMask;
-                    if (w1 != 0u) n1 = idg[w1 - 1] & kIdMask;
-                    if (w2 != 0u) n2 = idg[w2 - 1] & kIdMask;
-                    if (w3 != 0u) n3 = idg[w3 - 1] & kIdMask;
+                    if (w0 != 0u) n0 = id_of(w0 - 1) & kIdMask;
+                    if (w1 != 0u) n1 = id_of(w1 - 1) & kIdMask;
+                    if (w2 != 0u) n2 = id_of(w2 - 1) & kIdMask;
+                    if (w3 != 0u) n3 = id_of(w3 - 1) & kIdMask;
                     cswap(n0, n1); cswap(n2, n3); cswap(n0, n2); cswap(n1, n3); cswap(n1, n2);
                     if (n3 == n2) n3 = 0x7fffffff;
                     if (n2 == n1) { n2 = n3; n3 = 0x7fffffff; }
@@ -440,7 +448,7 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
                 int tot;
                 const int ex = block_excl_scan<B>(c, tot, sp);
                 if (r < nT) {
-                    const int32_t id = idg[r];
+                    const int32_t id = id_of(r);
                     if (id >= 0) s_status |= kStInconsistent;  // position r must be internal
                     const int o = ecarry + ex;
                     blk[lay.trows + r] = id & kIdMask;
@@ -580,12 +588,115 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
         }
         __syncthreads();  // cnt[r] = start of row r's list, cnt[r+1] = its end
         PHASE_MARK(3);
-        // ---- VT: a row's tetrahedra by original id; the offsets are the lists'
+        // ---- VV: one row per group of G lanes (16 or 32), in rounds of B/G
+        // rows.  The group marks the row's neighbours in its bitmap over the
+        // local table (the lanes that set a bit count the distinct ones); the
+        // round's counts give every row its offset after one barrier; the row
+        // is then read from the bitmap in word order, which is original id
+        // order, each lane taking a run of consecutive words.
+        if ((mask & kRelVV) && vt_ok) {
+            __shared__ int s_vc[2][B / 16];
+            const int W = pl.W;
+            int32_t *lvl = reinterpret_cast<int32_t *>(base + pl.lvl);
+            const int cap = it.cap_vv;
+            for (int i = tid; i < (B / pl.G) * W; i += B) wbm[i] = 0u;
+            if constexpr (kL)
+                for (int i = tid; i < L; i += B) lvl[i] = lvg[i] & kIdMask;
+            __syncthreads();
+            auto orig = [&](int l) -> int32_t {
+                if constexpr (kL) return lvl[l];
+                else return lvg[l] & kIdMask;
+            };
+            int base_off = 0;
+            auto rows_by = [&](auto gtag) {
+                constexpr int G = decltype(gtag)::value;
+                constexpr int NG = B / G;
+                const int grp = tid / G, gl = tid % G;
+                uint32_t *wb = wbm + (int64_t)grp * W;
+                const int K = (W + G - 1) / G;  // words per lane
+                const int wbeg = gl * K, wend = min(W, wbeg + K);
+                auto mark = [&](int v, int self) -> int {
+                    if (v == self) return 0;
+                    const uint32_t bit = 1u << (v & 31);
+                    return (atomicOr(&wb[v >> 5], bit) & bit) == 0u ? 1 : 0;
+                };
+                int par = 0;
+                for (int r0 = 0; r0 < nV; r0 += NG) {
+                    const int r = r0 + grp;
+                    int c = 0;
+                    if (r < nV) {
+                        const int self = rowl[r];
+                        for (int i = cnt[r] + gl; i < cnt[r + 1]; i += G) {
+                            const int4 t = tet(lvt[i]);
+                            c += mark(t.x, self) + mark(t.y, self) + mark(t.z, self) + mark(t.w, self);
+                        }
+                    }
+#pragma unroll
+                    for (int d = G / 2; d >= 1; d >>= 1) c += __shfl_xor(c, d, G);
+                    if (gl == 0) s_vc[par][grp] = c;
+                    __syncthreads();
+                    // this round's offsets: base + counts of the groups before
+                    int x = 0;
+                    for (int j = gl; j < NG; j += G) x += (j < grp) ? s_vc[par][j] : 0;
+                    int round_total = 0;
+                    for (int j = gl; j < NG; j += G) round_total += s_vc[par][j];
+#pragma unroll
+                    for (int d = G / 2; d >= 1; d >>= 1) {
+                        x += __shfl_xor(x, d, G);
+                        round_total += __shfl_xor(round_total, d, G);
+                    }
+                    const int o_row = base_off + x;
+                    par ^= 1;
+                    if (r < nV) {
+                        if (gl == 0) blk[lay.vv_off + r] = o_row;
+                        const bool fits = o_row + c <= cap;
+                        int n = 0;
+                        for (int w = wbeg; w < wend; ++w) n += __popc(wb[w]);
+                        int y = n;
+#pragma unroll
+                        for (int d = 1; d < G; d <<= 1) {
+                            const int z = __shfl_up(y, d, G);
+                            if (gl >= d) y += z;
+                        }
+                        int pos = o_row + y - n;
+                        for (int w = wbeg; w < wend; ++w) {
+                            uint32_t bits = wb[w];
+                            if (bits) {
+                                wb[w] = 0u;
+                                if (fits) {
+                                    while (bits) {
+                                        const int b = __ffs(bits) - 1;
+                                        bits &= bits - 1u;
+                                        blk[lay.vv_ent + pos] = orig(w * 32 + b);
+                                        ++pos;
+                                    }
+                                }
+                            }
+                        }
+                    }
+                    base_off += round_total;
+                }
+            };
+            if (pl.G == 16) rows_by(std::integral_constant<int, 16>{});
+            else rows_by(std::integral_constant<int, 32>{});
+            if (tid == 0) {
+                blk[lay.vv_off + nV] = base_off;
+                blk[4] = base_off;
+                if (base_off > cap) s_status |= kStVVOverflow;
+            }
+            __syncthreads();
+            PHASE_MARK(5);
+        }
+
+        // ---- VT: a row's tetrahedra by original id; the offsets are the lists'.
+        // LDS path: rows sorted by their threads into a buffer over the star
+        // tetrahedra's region (no longer needed), then copied out in order.
         if ((mask & kRelVT) && vt_ok) {
-            for (int r = tid; r < nV; r += B) {
+            int32_t *buf = reinterpret_cast<int32_t *>(smem + pl.lt);
+            const int bcap = kL ? (int)((pl.rix - pl.lt) / 4) : 0;
+            // sort row r's ids into dst (n <= 32 in registers, longer in place)
+            auto sort_row = [&](int r, int32_t *dst) {
                 const int s0 = cnt[r], n = cnt[r + 1] - s0;
-                blk[lay.vt_off + r] = s0;
-                int32_t *dst = blk + lay.vt_ent + s0;
                 if (n <= 32) {
                     uint32_t v[32];
 #pragma unroll
@@ -596,7 +707,6 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
                     for (int i = 0; i < 32; ++i)
                         if (i < n) dst[i] = (int32_t)v[i];
                 } else {
-                    // long rows (high valence): insertion sort in place
                     for (int i = 0; i < n; ++i) {
                         const int32_t x = idg[lvt[s0 + i]] & kIdMask;
                         int j = i - 1;
@@ -607,130 +717,41 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
                         dst[j + 1] = x;
                     }
                 }
-            }
+            };
+            for (int r = tid; r < nV; r += B) blk[lay.vt_off + r] = cnt[r];
             if (tid == 0) blk[lay.vt_off + nV] = cnt[nV];
-            __syncthreads();
+            if constexpr (!kL) {
+                for (int r = tid; r < nV; r += B) sort_row(r, blk + lay.vt_ent + cnt[r]);
+                __syncthreads();
+            } else {
+                int r0 = 0;
+                while (r0 < nV) {
+                    // rows [r0, r1): at most B of them, their entries within the buffer
+                    int lo = r0, hi = min(nV, r0 + B);
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (cnt[mid] - cnt[r0] <= bcap) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    const int r1 = lo;
+                    if (r1 == r0) {
+                        // row r0 alone exceeds the buffer: sorted in place in the block
+                        if (tid == 0) sort_row(r0, blk + lay.vt_ent + cnt[r0]);
+                        __syncthreads();
+                        r0 += 1;
+                        continue;
+                    }
+                    const int e0 = cnt[r0];
+                    const int r = r0 + tid;
+                    if (r < r1) sort_row(r, buf + (cnt[r] - e0));
+                    __syncthreads();
+                    const int ne = cnt[r1] - e0;
+                    for (int e = tid; e < ne; e += B) blk[lay.vt_ent + e0 + e] = buf[e];
+                    __syncthreads();
+                    r0 = r1;
+                }
+            }
             PHASE_MARK(4);
-        }
-
-        // ---- VV: one row at a time per group of 32 lanes.  Marking the row's
-        // neighbours in the group's bitmap over the local table removes
-        // repeats: the lane that sets a bit stages that vertex.  A staged
-        // vertex's place in the row is the number of staged vertices below it
-        // (local ids are in original id order).  Rows with more neighbours than
-        // the stage holds read them from the bitmap in word order instead.
-        if ((mask & kRelVV) && vt_ok) {
-            constexpr int G = 32;
-            constexpr int NG = B / G;
-            __shared__ int s_gcnt[NG];
-            const int W = pl.W;
-            const int grp = tid / G, gl = tid % G;
-            uint32_t *wb = wbm + (int64_t)grp * W;
-            LidT *stg = reinterpret_cast<LidT *>(base + pl.stg) + (int64_t)grp * kVVStage;
-            const int cap = it.cap_vv;
-            for (int w = gl; w < W; w += G) wb[w] = 0u;
-            if (gl == 0) s_gcnt[grp] = 0;
-            wave_fence();
-            auto mark = [&](int v, int self) {
-                if (v != self) {
-                    const uint32_t bit = 1u << (v & 31);
-                    if ((atomicOr(&wb[v >> 5], bit) & bit) == 0u) {
-                        const int k = atomicAdd(&s_gcnt[grp], 1);
-                        if (k < kVVStage) stg[k] = (LidT)v;
-                    }
-                }
-            };
-            // the distinct neighbours of row r; returns their count
-            auto gather = [&](int r) -> int {
-                const int self = rowl[r];
-                for (int i = cnt[r] + gl; i < cnt[r + 1]; i += G) {
-                    const int4 t = tet(lvt[i]);
-                    mark(t.x, self);
-                    mark(t.y, self);
-                    mark(t.z, self);
-                    mark(t.w, self);
-                }
-                wave_fence();
-                return s_gcnt[grp];
-            };
-            // clear what the row set: the staged vertices' words, or everything
-            auto clear = [&](int c) {
-                if (c <= kVVStage) {
-                    for (int k = gl; k < c; k += G) wb[stg[k] >> 5] = 0u;
-                } else {
-                    for (int w = gl; w < W; w += G) wb[w] = 0u;
-                }
-                wave_fence();
-                if (gl == 0) s_gcnt[grp] = 0;
-                wave_fence();
-            };
-            // pass 1: counts
-            for (int r = grp; r < nV; r += NG) {
-                const int c = gather(r);
-                if (gl == 0) blk[lay.vv_off + r] = c;  // the count, turned into the offset below
-                clear(c);
-            }
-            __syncthreads();
-            PHASE_MARK(5);
-            int carry = 0;
-            for (int r0 = 0; r0 < nV; r0 += B) {
-                const int r = r0 + tid;
-                const int x = r < nV ? blk[lay.vv_off + r] : 0;
-                int tot;
-                const int ex = block_excl_scan<B>(x, tot, sp);
-                if (r < nV) blk[lay.vv_off + r] = carry + ex;
-                carry += tot;
-            }
-            if (tid == 0) {
-                blk[lay.vv_off + nV] = carry;
-                blk[4] = carry;
-                if (carry > cap) s_status |= kStVVOverflow;
-            }
-            __syncthreads();
-            // pass 2: entries
-            if (carry <= cap) {
-                for (int r = grp; r < nV; r += NG) {
-                    const int c = gather(r);
-                    int32_t *dst = blk + lay.vv_ent + blk[lay.vv_off + r];
-                    if (c <= kVVStage) {
-                        const int v0 = gl < c ? (int)stg[gl] : 0x7fffffff;
-                        const int v1 = gl + G < c ? (int)stg[gl + G] : 0x7fffffff;
-                        int k0 = 0, k1 = 0;
-                        for (int j = 0; j < c; ++j) {
-                            const int x = stg[j];
-                            k0 += x < v0;
-                            k1 += x < v1;
-                        }
-                        if (gl < c) dst[k0] = lvg[v0] & kIdMask;
-                        if (gl + G < c) dst[k1] = lvg[v1] & kIdMask;
-                    } else {
-                        // many neighbours: the bitmap in word order
-                        int o = 0;
-                        for (int w0 = 0; w0 < W; w0 += G) {
-                            const int w = w0 + gl;
-                            uint32_t bits = w < W ? wb[w] : 0u;
-                            const int n = __popc(bits);
-                            int x = n;
-                            #pragma unroll
-                            for (int d = 1; d < G; d <<= 1) {
-                                const int y = __shfl_up(x, d, G);
-                                if (gl >= d) x += y;
-                            }
-                            const int tot = __shfl(x, G - 1, G);
-                            int pos = o + x - n;
-                            while (bits) {
-                                const int b = __ffs(bits) - 1;
-                                bits &= bits - 1u;
-                                dst[pos++] = lvg[w * 32 + b] & kIdMask;
-                            }
-                            o += tot;
-                        }
-                    }
-                    clear(c);
-                }
-            }
-            __syncthreads();
-            PHASE_MARK(6);
         }
     }
     __syncthreads();
@@ -844,13 +865,26 @@ hipError_t launch_persistent(const KArgs &a, bool lds_path, int block_threads, i
                     : launch_persistent_t<false>(a, block_threads, grid, 0, st);
 }
 
+static const void *const kLdsKernels[] = {
+    (const void *)gale_items_kernel<256, true>,      (const void *)gale_items_kernel<512, true>,
+    (const void *)gale_items_kernel<1024, true>,     (const void *)gale_persistent_kernel<256, true>,
+    (const void *)gale_persistent_kernel<512, true>, (const void *)gale_persistent_kernel<1024, true>,
+};
+
+hipError_t static_lds_bytes(int64_t *bytes) {
+    int64_t mx = 0;
+    for (const void *f : kLdsKernels) {
+        hipFuncAttributes at;
+        const hipError_t e = hipFuncGetAttributes(&at, f);
+        if (e != hipSuccess) return e;
+        mx = at.sharedSizeBytes > (size_t)mx ? (int64_t)at.sharedSizeBytes : mx;
+    }
+    *bytes = mx;
+    return hipSuccess;
+}
+
 hipError_t set_lds_limits(size_t lds) {
-    const void *fns[] = {
-        (const void *)gale_items_kernel<256, true>,       (const void *)gale_items_kernel<512, true>,
-        (const void *)gale_items_kernel<1024, true>,      (const void *)gale_persistent_kernel<256, true>,
-        (const void *)gale_persistent_kernel<512, true>,  (const void *)gale_persistent_kernel<1024, true>,
-    };
-    for (const void *f : fns) {
+    for (const void *f : kLdsKernels) {
         const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }

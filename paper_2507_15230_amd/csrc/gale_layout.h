@@ -145,20 +145,24 @@ GALE_HD BlockLayout block_layout(uint32_t mask, int32_t nV, int32_t nT, int32_t 
 //   cnt   local VT offsets of the rows, nV + 1
 //   lvt   local VT entries: stream positions, nnzVT
 //   wbm   one bitmap over the local vertex table per row group (VV)
-//   stg   the distinct neighbours of the row a group works on (VV)
+//   lvl   the original id of each local vertex (VV, LDS path)
+// VT runs last and writes its rows through a buffer over the star
+// tetrahedra's region (LDS path); TT reads tetrahedron ids from a copy in the
+// face table's region when it fits.
 struct Plan {
     int32_t ok;       // LDS path possible within the budget
     int32_t W;        // bitmap words per row
     int32_t H;        // face table cells
     int32_t P;        // face table passes (faces split by hash)
-    int64_t lt, win, ht, rix, rowl, cnt, lvt, wbm, stg;
+    int32_t G;        // lanes per VV row group (16 or 32)
+    int32_t pad;
+    int64_t lt, win, ht, rix, rowl, cnt, lvt, wbm, lvl;
     int64_t bytes;
 };
 
 GALE_HD int64_t align16(int64_t b) { return (b + 15) / 16 * 16; }
 
 constexpr int kMaxFacePasses = 16;
-constexpr int kVVStage = 64;  // distinct neighbours of a VV row staged per row group
 
 // Face table passes for H cells: distinct faces are estimated at 2.5 per TT
 // row (a closed region has 2 plus half its boundary) at load 0.7; the kernel
@@ -174,12 +178,14 @@ GALE_HD int32_t face_passes(int32_t nT, int64_t H) {
 // Face table cells kept per TT row at most (load about 1/3 on a closed region).
 GALE_HD int64_t face_cells_max(int32_t nT) { return 6 * (int64_t)nT + 64; }
 
-// VT / VV arrays from byte offset off (cell: bytes of an id or position);
-// returns the end.
-GALE_HD int64_t v_arrays(Plan &p, const ClusterMeta &m, uint32_t mask, int64_t off, int cell) {
+// VT / VV arrays from byte offset off (cell: bytes of an id or position),
+// with one VV bitmap per group of vv_group lanes; returns the end.
+GALE_HD int64_t v_arrays(Plan &p, const ClusterMeta &m, uint32_t mask, int64_t off, int cell, int block_threads,
+                         int vv_group) {
     const bool v = (mask & (kRelVT | kRelVV)) != 0;
     const bool vv = (mask & kRelVV) != 0;
-    const int64_t ngroups = 32;
+    const int64_t ngroups = block_threads / vv_group;
+    p.G = vv_group;
     p.W = (m.L + 31) / 32;
     p.rix = off;
     off += v ? align16((int64_t)m.L * cell) : 0;
@@ -191,8 +197,8 @@ GALE_HD int64_t v_arrays(Plan &p, const ClusterMeta &m, uint32_t mask, int64_t o
     off += v ? align16((int64_t)m.nnzVT * cell) : 0;
     p.wbm = off;
     off += vv ? align16(ngroups * (int64_t)p.W * 4) : 0;
-    p.stg = off;
-    off += vv ? align16(ngroups * (int64_t)kVVStage * cell) : 0;
+    p.lvl = off;
+    off += (vv && cell == 2) ? align16((int64_t)m.L * 4) : 0;
     return off;
 }
 
@@ -204,7 +210,6 @@ GALE_HD Plan lds_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32
     const bool narrow = m.L <= 65535 && ntot <= 65535;
     const bool tt = (mask & kRelTT) != 0;
     const bool v = (mask & (kRelVT | kRelVV)) != 0;
-    (void)block_threads;
     p.lt = 0;
     // TT: partner cells, then the table takes what is left (an even count)
     p.win = align16((int64_t)m.nT * 8);
@@ -216,8 +221,10 @@ GALE_HD Plan lds_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32
     p.H = (int32_t)h;
     p.P = tt ? face_passes(m.nT, h) : 0;
     const int64_t tt_end = p.ht + 2 * h;
-    // VT / VV after the star tetrahedra (the halo holds no vertex of C)
-    const int64_t v_end = v_arrays(p, m, mask, align16((int64_t)m.ns * 8), 2);
+    // VT / VV after the star tetrahedra (the halo holds no vertex of C); VV
+    // rows by groups of 16 lanes when their bitmaps fit, else 32
+    int64_t v_end = v_arrays(p, m, mask, align16((int64_t)m.ns * 8), 2, block_threads, 16);
+    if (v_end > budget) v_end = v_arrays(p, m, mask, align16((int64_t)m.ns * 8), 2, block_threads, 32);
     p.bytes = tt_end > v_end ? tt_end : v_end;
     const bool tt_ok = !tt || (h >= 64 && p.P <= kMaxFacePasses / 2 && tt_end <= budget);
     const bool v_ok = !v || v_end <= budget;
@@ -231,7 +238,6 @@ GALE_HD Plan lds_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32
 GALE_HD Plan ws_plan(const ClusterMeta &m, uint32_t mask, int32_t block_threads) {
     Plan p{};
     const bool tt = (mask & kRelTT) != 0;
-    (void)block_threads;
     p.ok = 1;
     p.lt = 0;
     p.win = 0;
@@ -240,7 +246,7 @@ GALE_HD Plan ws_plan(const ClusterMeta &m, uint32_t mask, int32_t block_threads)
     p.H = (int32_t)h;
     p.P = tt ? 1 : 0;
     const int64_t tt_end = p.ht + 4 * h;
-    const int64_t v_end = v_arrays(p, m, mask, 0, 4);
+    const int64_t v_end = v_arrays(p, m, mask, 0, 4, block_threads, 32);
     p.bytes = tt_end > v_end ? tt_end : v_end;
     return p;
 }
