@@ -132,7 +132,8 @@ gale_status gale_create(const gale_config *cfg, gale_ctx **out);
 
 /* Load a mesh (host arrays; copied, the caller keeps ownership).
  * tv: nt*4 vertex ids, row-major; cluster_of_vertex: nv cluster ids in
- * [0, nclusters).  Validates (EINVAL), prepares every cluster's star and halo
+ * [0, nclusters); nv and nt at most 2^30.  Validates (EINVAL), prepares every
+ * cluster's star and halo
  * stream and copies them to device memory.  May be called once per context. */
 gale_status gale_load(gale_ctx *ctx, int32_t nv, int64_t nt, const int32_t *tv,
                       const int32_t *cluster_of_vertex, int32_t nclusters);

@@ -44,7 +44,8 @@
 
 namespace gale {
 
-constexpr int32_t kIdMask = 0x7fffffff;
+constexpr int32_t kIdMask = 0x7fffffff;   // tetrahedron id (bit 31: internal)
+constexpr int32_t kVidMask = 0x3fffffff;  // vertex id (bit 31: row, bit 30: lower cluster)
 
 #ifdef GALE_PHASE_TIMING
 __device__ unsigned long long g_phase_cycles[32];
@@ -389,6 +390,35 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
         using Ins = std::integral_constant<bool, true>;
         using Look = std::integral_constant<bool, false>;
 
+        // lower-cluster vertices: a face holding one is no face of a TT row
+        uint32_t *lowb = reinterpret_cast<uint32_t *>(base + pl.lowb);
+        {
+            const int lane = tid & 63, nwords = (L + 31) >> 5;
+            for (int w0 = (tid >> 6) * 2; w0 < nwords; w0 += (B / 64) * 2) {
+                const int i = w0 * 32 + lane;
+                const unsigned long long bits = __ballot(i < L && (lvg[i] & 0x40000000));
+                if (lane == 0) {
+                    lowb[w0] = (uint32_t)bits;
+                    if (w0 + 1 < nwords) lowb[w0 + 1] = (uint32_t)(bits >> 32);
+                }
+            }
+        }
+        __syncthreads();
+        auto is_low = [&](int v) -> uint32_t { return (lowb[v >> 5] >> (v & 31)) & 1u; };
+        // the faces of a tetrahedron outside the rows worth looking up
+        auto look = [&](int4 s, int pass, int P, int me) {
+            const uint32_t lm = is_low(s.x) | is_low(s.y) << 1 | is_low(s.z) << 2 | is_low(s.w) << 3;
+#pragma unroll 1
+            for (int k = 0; k < 4; ++k) {
+                if (lm & ~(1u << k)) continue;  // a vertex of face k is in a lower cluster
+                int fa, fb, fc;
+                face_of(s, k, fa, fb, fc);
+                const uint32_t h = face_hash(fa, fb, fc);
+                if (P == 1 || (int)(((h & 0xFFFFu) * (uint32_t)P) >> 16) == pass)
+                    visit(Look{}, h, fa, fb, fc, me, k);
+            }
+        };
+
         int P = pl.P;
         while (true) {
             for (int i = tid; i < win_words; i += B) win32[i] = 0u;
@@ -399,7 +429,7 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
                 __syncthreads();
                 PHASE_MARK(7);
                 if (s_full) break;
-                for (int p = nT + tid; p < ntot; p += B) faces(Look{}, tet_global(p), pass, P, p);
+                for (int p = nT + tid; p < ntot; p += B) look(tet_global(p), pass, P, p);
                 __syncthreads();
                 PHASE_MARK(8);
             }
@@ -539,7 +569,7 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
                     rix[i] = row ? (LidT)r : kNoRow;
                     if (row) {
                         rowl[r] = (LidT)i;
-                        blk[lay.vrows + r] = lv & kIdMask;
+                        blk[lay.vrows + r] = lv & kVidMask;
                     }
                 }
                 carry += tot;
@@ -601,11 +631,11 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
             const int cap = it.cap_vv;
             for (int i = tid; i < (B / pl.G) * W; i += B) wbm[i] = 0u;
             if constexpr (kL)
-                for (int i = tid; i < L; i += B) lvl[i] = lvg[i] & kIdMask;
+                for (int i = tid; i < L; i += B) lvl[i] = lvg[i] & kVidMask;
             __syncthreads();
             auto orig = [&](int l) -> int32_t {
                 if constexpr (kL) return lvl[l];
-                else return lvg[l] & kIdMask;
+                else return lvg[l] & kVidMask;
             };
             int base_off = 0;
             auto rows_by = [&](auto gtag) {

@@ -6,8 +6,10 @@
 //
 //   lverts[lv_off .. lv_off+L)   local vertex table: the original ids of every
 //                                vertex of star(C), halo(C) and C itself, in
-//                                ascending original id; bit 31 set when the
-//                                vertex belongs to C (a VT/VV row).
+//                                ascending original id (ids below 2^30); bit
+//                                31 set when the vertex belongs to C (a VT/VV
+//                                row), bit 30 when its cluster is below C (no
+//                                tetrahedron internal to C has such a vertex).
 //   tets (bytes from tb_off)     the four local vertex ids of each stream
 //                                tetrahedron, ascending, as 4 x uint16 (8 B)
 //                                when the local table has at most 65535
@@ -137,6 +139,7 @@ GALE_HD BlockLayout block_layout(uint32_t mask, int32_t nV, int32_t nT, int32_t 
 //         (only the internal ones while TT runs; the rest is staged after)
 // TT uses the region after the internal tetrahedra for
 //   win   four partner cells per TT row (stream positions, one per face)
+//   lowb  one bit per local vertex: its cluster is below C
 //   ht    face table: H cells holding the stream position of a tetrahedron
 // cells are uint16 in LDS and int32 in the global workspace.  VT / VV use
 // the region after the star tetrahedra (in the workspace: from its start) for
@@ -156,7 +159,7 @@ struct Plan {
     int32_t P;        // face table passes (faces split by hash)
     int32_t G;        // lanes per VV row group (16 or 32)
     int32_t pad;
-    int64_t lt, win, ht, rix, rowl, cnt, lvt, wbm, lvl;
+    int64_t lt, win, lowb, ht, rix, rowl, cnt, lvt, wbm, lvl;
     int64_t bytes;
 };
 
@@ -213,7 +216,8 @@ GALE_HD Plan lds_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32
     p.lt = 0;
     // TT: partner cells, then the table takes what is left (an even count)
     p.win = align16((int64_t)m.nT * 8);
-    p.ht = p.win + (tt ? align16((int64_t)m.nT * 4 * 2) : 0);
+    p.lowb = p.win + (tt ? align16((int64_t)m.nT * 4 * 2) : 0);
+    p.ht = p.lowb + (tt ? align16((int64_t)((m.L + 31) / 32) * 4) : 0);
     int64_t h = tt ? (budget - p.ht) / 2 : 0;
     const int64_t hmax = face_cells_max(m.nT);
     h = h > hmax ? hmax : h;
@@ -241,7 +245,8 @@ GALE_HD Plan ws_plan(const ClusterMeta &m, uint32_t mask, int32_t block_threads)
     p.ok = 1;
     p.lt = 0;
     p.win = 0;
-    p.ht = tt ? align16((int64_t)m.nT * 4 * 4) : 0;
+    p.lowb = tt ? align16((int64_t)m.nT * 4 * 4) : 0;
+    p.ht = p.lowb + (tt ? align16((int64_t)((m.L + 31) / 32) * 4) : 0);
     const int64_t h = tt ? face_cells_max(m.nT) : 0;
     p.H = (int32_t)h;
     p.P = tt ? 1 : 0;

@@ -67,6 +67,10 @@ gale_status prepare_streams(int32_t nv, int64_t nt, const int32_t *tv, const int
         err = "more than 2^30 tetrahedra";
         return GALE_EINVAL;
     }
+    if ((int64_t)nv > 0x40000000LL) {
+        err = "more than 2^30 vertices";
+        return GALE_EINVAL;
+    }
     if (nt > 0 && !tv) {
         err = "tv is NULL";
         return GALE_EINVAL;
@@ -359,7 +363,9 @@ gale_status prepare_streams(int32_t nv, int64_t nt, const int32_t *tv, const int
                     const ClusterMeta &m = out.meta[k];
                     for (int32_t l = 0; l < m.L; ++l) {
                         const int32_t v = tab[l];
-                        out.lverts[m.lv_off + l] = cl[v] == k ? (int32_t)((uint32_t)v | 0x80000000u) : v;
+                        const uint32_t row = cl[v] == k ? 0x80000000u : 0u;
+                        const uint32_t lower = cl[v] < k ? 0x40000000u : 0u;
+                        out.lverts[m.lv_off + l] = (int32_t)((uint32_t)v | row | lower);
                     }
                     auto local = [&](int32_t v) -> int32_t {
                         return (int32_t)(std::lower_bound(tab.begin(), tab.end(), v) - tab.begin());
