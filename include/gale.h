@@ -125,6 +125,11 @@ typedef struct {
     /* mean per-request stage times, microseconds: queued (submit -> admitted),
        build (admitted -> kernel done), copy (kernel done -> host copy done) */
     double   stage_queue_us, stage_build_us, stage_copy_us;
+    /* DIRECT mode, BATCHED form: duration of the persistent LDS-path kernel
+       launches, from HIP events recorded around each launch on the context
+       stream */
+    uint64_t timed_launches;
+    double   kernel_ms_total;
 } gale_stats;
 
 /* Create a context on cfg->device.  cfg may be NULL for defaults. */

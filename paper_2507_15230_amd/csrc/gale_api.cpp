@@ -125,11 +125,19 @@ KArgs base_args(const gale_ctx *ctx) {
     return a;
 }
 
+void destroy_ticket_events(Ticket *t) {
+    for (hipEvent_t &e : t->batch.kev) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
+}
+
 // Launch items already uploaded in launch order: the first n_lds take the
 // LDS path, the next n_glob the global-workspace path.  PLAIN: one launch per
 // item; BATCHED: one persistent launch per path, each with its own queue word.
 gale_status launch_batch(gale_ctx *ctx, int form, int32_t *d_out, int32_t *d_hdr, const WorkItem *d_items,
-                         int n_lds, int n_glob, int32_t *d_queue, char *d_ws, int64_t ws_stride, hipStream_t st) {
+                         int n_lds, int n_glob, int32_t *d_queue, char *d_ws, int64_t ws_stride, hipStream_t st,
+                         const hipEvent_t *kev, bool *kev_recorded) {
     KArgs a = base_args(ctx);
     a.out = d_out;
     a.hdr = d_hdr;
@@ -148,8 +156,12 @@ gale_status launch_batch(gale_ctx *ctx, int form, int32_t *d_out, int32_t *d_hdr
             a.items = d_items;
             a.nitems = n_lds;
             a.queue = d_queue;
-            e = launch_persistent(a, true, ctx->block_threads, std::min<int>(n_lds, ctx->grid_lds), ctx->lds_budget,
-                                  st);
+            if (kev) e = hipEventRecord(kev[0], st);
+            if (e == hipSuccess)
+                e = launch_persistent(a, true, ctx->block_threads, std::min<int>(n_lds, ctx->grid_lds),
+                                      ctx->lds_budget, st);
+            if (kev && e == hipSuccess) e = hipEventRecord(kev[1], st);
+            if (kev && kev_recorded && e == hipSuccess) *kev_recorded = true;
             ctx->n_launches++;
         }
         if (n_glob > 0 && e == hipSuccess) {
@@ -168,7 +180,8 @@ gale_status launch_batch(gale_ctx *ctx, int form, int32_t *d_out, int32_t *d_hdr
 // launch order with two zero queue words, and launch.  Buffers come from the
 // pools; the caller releases them.
 gale_status upload_and_launch(gale_ctx *ctx, int form, const std::vector<WorkItem> &items, int32_t *d_out,
-                              Buf *&dev_items, Buf *&dev_hdr, Buf *&host_items, Buf *&ws, hipStream_t st) {
+                              Buf *&dev_items, Buf *&dev_hdr, Buf *&host_items, Buf *&ws, hipStream_t st,
+                              const hipEvent_t *kev, bool *kev_recorded) {
     hipError_t e;
     const int n = (int)items.size();
     std::vector<WorkItem> order;
@@ -197,7 +210,7 @@ gale_status upload_and_launch(gale_ctx *ctx, int form, const std::vector<WorkIte
     if (e != hipSuccess) return fail(GALE_EDEVICE, std::string("work list copy: ") + hipGetErrorString(e));
     char *di = (char *)dev_items->ptr;
     return launch_batch(ctx, form, d_out, (int32_t *)dev_hdr->ptr, (const WorkItem *)(di + 64), n_lds, n_glob,
-                        (int32_t *)di, ws ? (char *)ws->ptr : nullptr, wsb, st);
+                        (int32_t *)di, ws ? (char *)ws->ptr : nullptr, wsb, st, kev, kev_recorded);
 }
 
 // Lay out the batch's items in a fresh output buffer and launch them.
@@ -211,7 +224,7 @@ gale_status run_items(gale_ctx *ctx, Batch &b, int form, hipStream_t st) {
     if (!b.host_hdr) return fail(GALE_ENOMEM, "batch buffers");
     if (n == 0) return GALE_OK;
     return upload_and_launch(ctx, form, b.items, (int32_t *)b.out->ptr, b.dev_items, b.dev_hdr, b.host_items, b.ws,
-                             st);
+                             st, b.kev[0] ? b.kev : nullptr, &b.kev_recorded);
 }
 
 void release_batch(gale_ctx *ctx, Batch &b) {
@@ -430,6 +443,11 @@ gale_status direct_build(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t 
     for (size_t i = 0; i < t->batch.items.size(); ++i)
         t->by_cluster[t->batch.items[i].cluster].push_back((int)i);
     std::lock_guard<std::mutex> g(ctx->direct_mu);
+    if (form == GALE_FORM_BATCHED) {
+        // kernel timing: events around the persistent LDS-path launch
+        if (hipEventCreate(&t->batch.kev[0]) != hipSuccess || hipEventCreate(&t->batch.kev[1]) != hipSuccess)
+            destroy_ticket_events(t);
+    }
     s = run_items(ctx, t->batch, form, ctx->stream);
     if (s == GALE_OK) {
         hipError_t e = hipEventCreateWithFlags(&t->done, hipEventDisableTiming);
@@ -440,6 +458,7 @@ gale_status direct_build(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t 
         if (s == GALE_EDEVICE) ctx->poisoned = true;
         release_batch(ctx, t->batch);
         if (t->done) (void)hipEventDestroy(t->done);
+        destroy_ticket_events(t);
         delete t;
         return s;
     }
@@ -470,6 +489,13 @@ gale_status direct_poll(gale_ctx *ctx, Ticket *t, int64_t timeout_ns) {
     }
     std::lock_guard<std::mutex> g(ctx->direct_mu);
     if (t->ready) return t->status;
+    if (t->batch.kev_recorded) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, t->batch.kev[0], t->batch.kev[1]) == hipSuccess) {
+            ctx->kernel_ms += ms;
+            ctx->n_timed++;
+        }
+    }
     gale_status s = finalize_batch(ctx, t->batch, ctx->stream);
     if (s == GALE_OK && t->host) s = copy_batch_to_host(ctx, t->batch, ctx->stream);
     if (s == GALE_EDEVICE) ctx->poisoned = true;
@@ -687,6 +713,7 @@ gale_status gale_release(gale_ctx *ctx, uint64_t ticket) {
     }
     if (!t->ready) (void)hipEventSynchronize(t->done);
     if (t->done) (void)hipEventDestroy(t->done);
+    destroy_ticket_events(t);
     for (Buf *b : t->batch.extra) ctx->dev_pool.release(b);
     release_batch(ctx, t->batch);
     delete t;
@@ -713,12 +740,22 @@ gale_status gale_get_stats(gale_ctx *ctx, gale_stats *out) {
     out->tt_exhaustive_blocks = ctx->n_tt_exhaustive;
     out->entries_delivered = ctx->n_delivered;
     out->bytes_d2h = ctx->n_bytes_d2h;
+    {
+        std::lock_guard<std::mutex> g(ctx->direct_mu);
+        out->timed_launches = ctx->n_timed;
+        out->kernel_ms_total = ctx->kernel_ms;
+    }
     if (ctx->cfg.mode == GALE_MODE_SERVE) serve_stats(ctx, out);
     return GALE_OK;
 }
 
 gale_status gale_reset_stats(gale_ctx *ctx) {
     if (!ctx) return fail(GALE_EINVAL, "ctx is NULL");
+    {
+        std::lock_guard<std::mutex> g(ctx->direct_mu);
+        ctx->n_timed = 0;
+        ctx->kernel_ms = 0.0;
+    }
     if (ctx->cfg.mode == GALE_MODE_SERVE) serve_reset_stats(ctx);
     return GALE_OK;
 }
@@ -733,6 +770,7 @@ void gale_destroy(gale_ctx *ctx) {
         for (auto &kv : ctx->tickets) {
             Ticket *t = kv.second;
             if (t->done) (void)hipEventDestroy(t->done);
+            destroy_ticket_events(t);
             delete t;
         }
         ctx->tickets.clear();

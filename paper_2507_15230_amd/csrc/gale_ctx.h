@@ -51,6 +51,8 @@ struct Batch {
     std::vector<BlockLoc> loc;          // where each item's block lives, after finalize
     std::vector<int64_t> host_word;     // host copy offsets
     bool host_ready = false;
+    hipEvent_t kev[2] = {nullptr, nullptr};  // around the persistent LDS-path launch (DIRECT, BATCHED)
+    bool kev_recorded = false;
 };
 
 struct Ticket {
@@ -154,6 +156,8 @@ struct gale_ctx {
     // counters
     std::atomic<uint64_t> n_requests{0}, n_blocks{0}, n_entries{0}, n_launches{0}, n_overflow{0},
         n_global_blocks{0}, n_delivered{0}, n_bytes_d2h{0}, n_tt_exhaustive{0};
+    uint64_t n_timed = 0;     // timed persistent launches (under direct_mu)
+    double kernel_ms = 0.0;   // their total duration
     gale::Serve serve;
 };
 
@@ -163,7 +167,8 @@ int32_t default_cap_tt(const ClusterMeta &m);
 int64_t lay_out_items(const gale_ctx *ctx, std::vector<WorkItem> &items, int64_t out_base_word);
 int64_t workspace_bytes(const gale_ctx *ctx, const std::vector<WorkItem> &items, int *n_global);
 gale_status upload_and_launch(gale_ctx *ctx, int form, const std::vector<WorkItem> &items, int32_t *d_out,
-                              Buf *&dev_items, Buf *&dev_hdr, Buf *&host_items, Buf *&ws, hipStream_t st);
+                              Buf *&dev_items, Buf *&dev_hdr, Buf *&host_items, Buf *&ws, hipStream_t st,
+                              const hipEvent_t *kev = nullptr, bool *kev_recorded = nullptr);
 gale_status check_request(const gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t mask);
 
 gale_status serve_start(gale_ctx *ctx);

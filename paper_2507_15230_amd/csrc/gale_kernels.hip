@@ -862,6 +862,7 @@ __global__ __launch_bounds__(B) void gale_persistent_kernel(KArgs a) {
 // ---------------------------------------------------------------------------
 template <bool kL>
 static hipError_t launch_items_t(const KArgs &a, int block_threads, int grid, size_t lds, hipStream_t st) {
+    (void)hipGetLastError();  // the launch status below is this launch's, not an earlier call's
     if (block_threads == 1024) {
         hipLaunchKernelGGL((gale_items_kernel<1024, kL>), dim3(grid), dim3(1024), lds, st, a);
     } else if (block_threads == 512) {
@@ -874,6 +875,7 @@ static hipError_t launch_items_t(const KArgs &a, int block_threads, int grid, si
 
 template <bool kL>
 static hipError_t launch_persistent_t(const KArgs &a, int block_threads, int grid, size_t lds, hipStream_t st) {
+    (void)hipGetLastError();  // the launch status below is this launch's, not an earlier call's
     if (block_threads == 1024) {
         hipLaunchKernelGGL((gale_persistent_kernel<1024, kL>), dim3(grid), dim3(1024), lds, st, a);
     } else if (block_threads == 512) {

@@ -35,12 +35,12 @@ def test_struct_layout_matches_binding(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gale.h"\n'
                    'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(gale_config), sizeof(gale_csr),'
-                   ' sizeof(gale_stats), offsetof(gale_csr, entries), offsetof(gale_stats, stage_copy_us));return 0;}\n')
+                   ' sizeof(gale_stats), offsetof(gale_csr, entries), offsetof(gale_stats, kernel_ms_total));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     assert got == [C.sizeof(gale.GaleConfig), C.sizeof(gale.GaleCsr), C.sizeof(gale.GaleStats),
-                   gale.GaleCsr.entries.offset, gale.GaleStats.stage_copy_us.offset]
+                   gale.GaleCsr.entries.offset, gale.GaleStats.kernel_ms_total.offset]
 
 
 def test_strerror_and_last_error():
