@@ -149,6 +149,54 @@ def cpu_baseline(mesh, budget_s: float = 15.0):
     }
 
 
+def serving_leg(mesh, args, pass_bytes: int):
+    """Consumer threads (native, in the library) classify critical points
+    cluster by cluster (Morton order, Zipf(1.1) re-access), first through the
+    serving loop (continuous batching, HBM cache under a budget), then through
+    synchronous plain per-cluster launches with no cache; per-access latency
+    (submit -> ready) percentiles."""
+    import meshgen
+    from paper_2507_15230_amd import gale
+    n = int(round(mesh.nv ** (1.0 / 3.0)))
+    field = meshgen.gauss_field(mesh.coords.astype(np.float64), n, np.random.default_rng(1))
+    budget = (args.serving_budget_mb << 20) if args.serving_budget_mb else pass_bytes // 2
+    order = np.arange(mesh.nclusters, dtype=np.int32)  # cluster ids are in Morton order
+    log("serving leg: %d consumers, budget %.0f MB" % (args.consumers, budget / 1e6))
+    ctx = gale.Context(device=0, mode="serve", cache_budget_bytes=budget, max_inflight=4,
+                       block_threads=args.block_threads)
+    ctx.load(mesh.tets, mesh.cluster, mesh.nclusters)
+    res = gale.consumer_run(ctx, mesh.tets, field, order, threads=args.consumers)
+    st = ctx.stats()
+    ctx.close()
+    out = {
+        "workload": "the benchmark mesh with a 16-Gaussian scalar field; %d native consumer threads, Morton "
+                    "cursor, truncated Zipf(1.1) re-access, VT+VV+TT per access, critical points from VT and VV"
+                    % args.consumers,
+        "consumers": args.consumers, "cache_budget_bytes": int(budget), "max_inflight": 4,
+        "accesses": res["accesses"], "reaccesses": res["reaccesses"], "wall_s": res["wall_s"],
+        "accesses_per_s": res["accesses"] / res["wall_s"],
+        "p50_us": res["lat_p50_us"], "p99_us": res["lat_p99_us"], "mean_us": res["lat_mean_us"],
+        "max_us": res["lat_max_us"],
+        "cache_hits": st["cache_hits"], "cache_misses": st["cache_misses"], "evictions": st["evictions"],
+        "batches": st["batches"], "mean_batch_clusters": st["mean_batch_clusters"],
+        "entries_built_per_s": st["entries_built"] / res["wall_s"],
+        "entries_delivered_per_s": st["entries_delivered"] / res["wall_s"],
+        "stage_us": {"queue": st["stage_queue_us"], "build": st["stage_build_us"], "copy": st["stage_copy_us"]},
+        "label_mismatches": res["mismatches"], "errors": res["errors"],
+        "critical_points": {"minima": res["minima"], "maxima": res["maxima"], "saddles": res["saddles"]},
+    }
+    log("plain serving baseline")
+    pctx = gale.Context(device=0, mode="direct", form="plain", block_threads=args.block_threads)
+    pctx.load(mesh.tets, mesh.cluster, mesh.nclusters)
+    pres = gale.consumer_run(pctx, mesh.tets, field, order, threads=args.consumers)
+    pctx.close()
+    out["plain"] = {"accesses": pres["accesses"], "wall_s": pres["wall_s"],
+                    "accesses_per_s": pres["accesses"] / pres["wall_s"],
+                    "p50_us": pres["lat_p50_us"], "p99_us": pres["lat_p99_us"], "mean_us": pres["lat_mean_us"],
+                    "label_mismatches": pres["mismatches"], "errors": pres["errors"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +207,10 @@ def main():
     ap.add_argument("--lds-bytes", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--consumers", type=int, default=40)
+    ap.add_argument("--serving-budget-mb", type=int, default=0,
+                    help="HBM cache budget of the serving leg; 0 = half of one full pass's block bytes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one %d MiB device copy (reference for the HBM byte counters)" % (COPY_BYTES >> 20))
     ap.add_argument("--summarize-profile", nargs=8, metavar=("KT", "FETCH", "WRITE", "MD", "JSON", "CMD_KT",
@@ -257,6 +309,10 @@ def main():
         plain = {"value": entries_step / pdt, "unit": "entries/s", "launches": 3 * ncl,
                  "ms_per_pass": pdt * 1000.0}
 
+    serving = None
+    if not args.no_serving:
+        serving = serving_leg(mesh, args, output_bytes(entries_step, nv, nt, ncl))
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -297,6 +353,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "plain": plain,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

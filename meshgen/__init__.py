@@ -242,7 +242,7 @@ def _permute(rng: np.random.Generator, tets, cluster, coords, scalar):
     return new_tets, new_cl, new_coords, new_scalar
 
 
-def _gauss_field(coords: np.ndarray, n: int, rng: np.random.Generator, ng: int = 16) -> np.ndarray:
+def gauss_field(coords: np.ndarray, n: int, rng: np.random.Generator, ng: int = 16) -> np.ndarray:
     """f = sum_g a_g exp(-|x-mu_g|^2/(2 s_g^2)) + 1e-3 U[0,1); draw order a (16),
     s (16), mu (16x3), then the noise (one per vertex).  float32."""
     box = float(n - 1)
@@ -287,7 +287,7 @@ def refined_mesh(n: int, frac: float, rounds: int, median: float, sigma: float, 
     coords = coords + rng.uniform(-0.2, 0.2, size=coords.shape)
     coords, tets = refine(coords, tets, n, frac, rounds, rng)
     cluster, ncl = clusters_lognormal(coords, median, sigma, lo, hi, rng)
-    scalar = _gauss_field(coords, n, rng) if with_scalar else None
+    scalar = gauss_field(coords, n, rng) if with_scalar else None
     coords32 = coords.astype(np.float32)
     tets, cluster, coords32, scalar = _permute(rng, tets, cluster, coords32, scalar)
     return Mesh(tets=np.ascontiguousarray(tets, dtype=np.int32), cluster=cluster.astype(np.int32),

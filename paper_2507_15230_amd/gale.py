@@ -57,6 +57,24 @@ class GaleStats(C.Structure):
     ]
 
 
+class GaleConsumerCfg(C.Structure):
+    _fields_ = [
+        ("threads", C.c_int32), ("n_order", C.c_int32), ("cluster_order", C.POINTER(C.c_int32)),
+        ("rel_mask", C.c_uint32), ("pad", C.c_int32), ("seed", C.c_uint64), ("zipf_s", C.c_double),
+        ("tets", C.POINTER(C.c_int32)), ("nt", C.c_int64), ("field", C.POINTER(C.c_float)),
+        ("nv", C.c_int32), ("pad2", C.c_int32),
+    ]
+
+
+class GaleConsumerResult(C.Structure):
+    _fields_ = [
+        ("accesses", C.c_uint64), ("reaccesses", C.c_uint64), ("mismatches", C.c_uint64), ("errors", C.c_uint64),
+        ("clusters", C.c_uint64), ("minima", C.c_uint64), ("maxima", C.c_uint64), ("saddles", C.c_uint64),
+        ("regular", C.c_uint64), ("wall_s", C.c_double), ("lat_p50_us", C.c_double), ("lat_p99_us", C.c_double),
+        ("lat_mean_us", C.c_double), ("lat_max_us", C.c_double), ("first_error", C.c_int32), ("pad", C.c_int32),
+    ]
+
+
 class GaleError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         super().__init__("%s: %s (%s) %s" % (where, _NAMES.get(status, status), status, detail))
@@ -92,6 +110,9 @@ def load_library(path: str = LIB_PATH):
         "gale_strerror": ([C.c_int32], C.c_char_p),
         "gale_last_error": ([], C.c_char_p),
         "gale_destroy": ([vp], None),
+        "gale_lowerstar_classify": ([C.c_int32, i32p, i32p, i32p, i32p, i32p, i32p, C.c_int64,
+                                     C.POINTER(C.c_float), C.c_int32, i32p], C.c_int32),
+        "gale_consumer_run": ([vp, C.POINTER(GaleConsumerCfg), C.POINTER(GaleConsumerResult)], C.c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -221,3 +242,49 @@ class Context:
 
 def strerror(status: int) -> str:
     return load_library().gale_strerror(int(status)).decode()
+
+
+CP_REGULAR, CP_MINIMUM, CP_MAXIMUM, CP_SADDLE = 0, 1, 2, 3
+
+
+def lowerstar_classify(rows, vt, vv, tets, field) -> np.ndarray:
+    """Critical-point label of every row of one cluster from its VT and VV
+    blocks (each a (row_ids, offsets, entries) triple as returned by
+    Context.block), the mesh tetrahedra and a float32 field; see
+    include/gale_lowerstar.h.  Runs on the calling thread (the GIL is released)."""
+    lib = load_library()
+    i32 = C.POINTER(C.c_int32)
+    rows = np.ascontiguousarray(rows, np.int32)
+    vt_off, vt_ent = (np.ascontiguousarray(a, np.int32) for a in vt[1:])
+    vv_off, vv_ent = (np.ascontiguousarray(a, np.int32) for a in vv[1:])
+    tets = np.ascontiguousarray(tets, np.int32)
+    field = np.ascontiguousarray(field, np.float32)
+    out = np.empty(rows.shape[0], np.int32)
+    st = lib.gale_lowerstar_classify(int(rows.shape[0]), rows.ctypes.data_as(i32), vt_off.ctypes.data_as(i32),
+                                     vt_ent.ctypes.data_as(i32), vv_off.ctypes.data_as(i32),
+                                     vv_ent.ctypes.data_as(i32), tets.ctypes.data_as(i32), int(tets.shape[0]),
+                                     field.ctypes.data_as(C.POINTER(C.c_float)), int(field.shape[0]),
+                                     out.ctypes.data_as(i32))
+    if st != 0:
+        raise GaleError(EINVAL, "gale_lowerstar_classify", "invalid block or id out of range")
+    return out
+
+
+def consumer_run(ctx: "Context", tets, field, cluster_order, threads: int = 40, mask: int = 7, seed: int = 0,
+                 zipf_s: float = 1.1) -> dict:
+    """Run the consumer workload with native threads against ctx (see
+    include/gale_lowerstar.h); returns the result fields as a dict."""
+    lib = load_library()
+    order = np.ascontiguousarray(cluster_order, np.int32)
+    tets = np.ascontiguousarray(tets, np.int32)
+    field = np.ascontiguousarray(field, np.float32)
+    i32 = C.POINTER(C.c_int32)
+    cfg = GaleConsumerCfg(threads=int(threads), n_order=int(order.shape[0]), cluster_order=order.ctypes.data_as(i32),
+                          rel_mask=int(mask), seed=int(seed), zipf_s=float(zipf_s), tets=tets.ctypes.data_as(i32),
+                          nt=int(tets.shape[0]), field=field.ctypes.data_as(C.POINTER(C.c_float)),
+                          nv=int(field.shape[0]))
+    res = GaleConsumerResult()
+    st = lib.gale_consumer_run(ctx._h, C.byref(cfg), C.byref(res))
+    if st != OK:
+        raise GaleError(st, "gale_consumer_run", "bad argument")
+    return {name: getattr(res, name) for name, _ in GaleConsumerResult._fields_ if not name.startswith("pad")}

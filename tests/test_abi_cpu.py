@@ -9,20 +9,23 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "gale.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def _declared():
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(gale_[a-z_]+)\s*\(", txt)))
+    names = set()
+    for h in HEADERS:
+        txt = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(gale_[a-z_]+)\s*\(", txt))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
     from paper_2507_15230_amd import gale
     lib = gale.load_library()
     names = _declared()
-    assert len(names) >= 14
+    assert len(names) >= 16
     for n in names:
         assert hasattr(lib, n), "libgale.so does not export " + n
     out = subprocess.run(["nm", "-D", "--defined-only", gale.LIB_PATH], capture_output=True, text=True).stdout
@@ -33,14 +36,18 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layout_matches_binding(tmp_path):
     from paper_2507_15230_amd import gale
     src = tmp_path / "sz.c"
-    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gale.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(gale_config), sizeof(gale_csr),'
-                   ' sizeof(gale_stats), offsetof(gale_csr, entries), offsetof(gale_stats, kernel_ms_total));return 0;}\n')
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gale.h"\n#include "gale_lowerstar.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gale_config),'
+                   ' sizeof(gale_csr), sizeof(gale_stats), offsetof(gale_csr, entries),'
+                   ' offsetof(gale_stats, kernel_ms_total), sizeof(gale_consumer_cfg), sizeof(gale_consumer_result),'
+                   ' offsetof(gale_consumer_cfg, nv), offsetof(gale_consumer_result, first_error));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     assert got == [C.sizeof(gale.GaleConfig), C.sizeof(gale.GaleCsr), C.sizeof(gale.GaleStats),
-                   gale.GaleCsr.entries.offset, gale.GaleStats.kernel_ms_total.offset]
+                   gale.GaleCsr.entries.offset, gale.GaleStats.kernel_ms_total.offset,
+                   C.sizeof(gale.GaleConsumerCfg), C.sizeof(gale.GaleConsumerResult),
+                   gale.GaleConsumerCfg.nv.offset, gale.GaleConsumerResult.first_error.offset]
 
 
 def test_strerror_and_last_error():

@@ -160,3 +160,65 @@ def test_serve_destroy_with_requests_in_flight():
     for k in range(m.nclusters):
         ctx.submit([k], 7)
     ctx.close()  # drains in-flight batches, fails what is still queued
+
+
+def test_consumers_classify_like_the_oracle():
+    """The serving workload (consumer threads, Zipf re-access, a budget that
+    forces evictions): every access's critical-point labels equal those from the
+    oracle's blocks, and re-accesses reproduce them."""
+    gale = _gale()
+    from paper_2507_15230_amd import workload
+    m = meshgen.grid_mesh(16, 64, seed=6)
+    field = meshgen.gauss_field(m.coords.astype(np.float64), 16, np.random.default_rng(2))
+    orc = oracle.Oracle.of(m)
+    exp = {}
+    for k in range(m.nclusters):
+        vt, vv = orc.block(k, 1), orc.block(k, 2)
+        exp[k] = gale.lowerstar_classify(vt[0], vt, vv, m.tets, field)
+    with gale.Context(mode="serve", cache_budget_bytes=256 << 10, max_inflight=3) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        got = {}
+        base = workload.served_request(ctx)
+
+        def request(c):
+            vt, vv, release = base(c)
+            lab = gale.lowerstar_classify(vt[0], vt, vv, m.tets, field)
+            got.setdefault(c, []).append(lab)
+            return vt, vv, release
+        res = workload.run_consumers(request, m.tets, field, range(m.nclusters), threads=12, seed=3)
+        st = ctx.stats()
+    _say("consumers", {k: res[k] for k in ("accesses", "reaccesses", "mismatches", "clusters")},
+         "evictions", st["evictions"])
+    assert not res["errors"], res["errors"]
+    assert res["mismatches"] == 0
+    assert res["clusters"] == m.nclusters
+    assert res["reaccesses"] > 0
+    for c, labs in got.items():
+        for lab in labs:
+            assert np.array_equal(lab, exp[c])
+
+
+@pytest.mark.parametrize("mode", ["serve", "plain"])
+def test_native_consumers_count_like_the_oracle(mode):
+    """Native consumer threads (gale_consumer_run) through the serving loop and
+    through plain per-cluster launches: no errors, no label changes between
+    accesses, and the critical points counted at each cluster's first access
+    equal those from the oracle's blocks."""
+    gale = _gale()
+    m = meshgen.grid_mesh(16, 64, seed=8)
+    field = meshgen.gauss_field(m.coords.astype(np.float64), 16, np.random.default_rng(4))
+    orc = oracle.Oracle.of(m)
+    tot = np.zeros(4, np.int64)
+    for k in range(m.nclusters):
+        vt, vv = orc.block(k, 1), orc.block(k, 2)
+        tot += np.bincount(gale.lowerstar_classify(vt[0], vt, vv, m.tets, field), minlength=4)
+    kw = dict(mode="serve", cache_budget_bytes=256 << 10, max_inflight=3) if mode == "serve" else \
+        dict(mode="direct", form="plain")
+    with gale.Context(**kw) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        res = gale.consumer_run(ctx, m.tets, field, np.arange(m.nclusters), threads=24, seed=5)
+    _say(mode, {k: res[k] for k in ("accesses", "reaccesses", "mismatches", "errors", "lat_p50_us", "lat_p99_us")})
+    assert res["errors"] == 0 and res["first_error"] == 0
+    assert res["mismatches"] == 0
+    assert res["clusters"] == m.nclusters
+    assert [res["regular"], res["minima"], res["maxima"], res["saddles"]] == tot.tolist()
