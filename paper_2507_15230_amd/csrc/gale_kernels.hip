@@ -49,6 +49,14 @@ constexpr int32_t kVidMask = 0x3fffffff;  // vertex id (bit 31: row, bit 30: low
 
 #ifdef GALE_PHASE_TIMING
 __device__ unsigned long long g_phase_cycles[32];
+// wave-level event counters (phase-timing builds only): slot k += 1 once per
+// wave that reaches the mark with at least one active lane
+#define WAVE_COUNT(k)                                                                      \
+    do {                                                                                   \
+        const unsigned long long act_ = __ballot(1);                                       \
+        if ((int)(threadIdx.x & 63) == __ffsll((long long)act_) - 1)                       \
+            atomicAdd(&g_phase_cycles[(k)], 1ull);                                         \
+    } while (0)
 #define PHASE_MARK(k)                                                              \
     do {                                                                           \
         __syncthreads();                                                           \
@@ -59,6 +67,9 @@ __device__ unsigned long long g_phase_cycles[32];
         }                                                                          \
     } while (0)
 #else
+#define WAVE_COUNT(k) \
+    do {              \
+    } while (0)
 #define PHASE_MARK(k) \
     do {              \
     } while (0)
@@ -347,46 +358,6 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
         const int win_words = kL ? 2 * nT : 4 * nT;  // 4 cells per row
         const int ht_words = kL ? H / 2 : H;
 
-        // Walk the chain of face {fa < fb < fc} (linear probing).  kIns: enter
-        // it (internal tetrahedron me, its face kme) or only look it up.
-        auto visit = [&](auto ins_tag, uint32_t h, int fa, int fb, int fc, int me, int kme) {
-            constexpr bool kIns = decltype(ins_tag)::value;
-            uint32_t idx = (uint32_t)(((unsigned long long)h * (uint32_t)H) >> 32);
-            int left = H + 2;  // a failed swap re-reads its cell; each cell changes once
-            bool active = true;
-            while (active) {
-                uint32_t w;
-                const uint32_t c = CL::read(ht, idx, w);
-                const int q = c == 0u ? 0 : (int)c - 1;
-                // the holder's face that is {fa, fb, fc}, if any (a tetrahedron
-                // meets its own earlier faces on the way: skip them)
-                const int kq = face_index(tet(q), fa, fb, fc);
-                const bool hit = c != 0u && q != me && kq >= 0;
-                bool stop = hit || (c == 0u && !kIns);
-                if (kIns && c == 0u) stop = CL::try_set(ht, idx, w, (uint32_t)me + 1u);
-                if (hit) {
-                    bool bad = CL::mark(win, 4 * (uint32_t)q + kq, (uint32_t)me + 1u);
-                    if (kIns) bad |= CL::mark(win, 4 * (uint32_t)me + kme, c);
-                    if (bad) s_fail = 1;
-                }
-                if (c != 0u && !hit) idx = idx + 1 == (uint32_t)H ? 0u : idx + 1;
-                if (--left == 0 && !stop) {
-                    if (kIns) s_full = 1;
-                    stop = true;
-                }
-                active = !stop;
-            }
-        };
-        auto faces = [&](auto ins_tag, int4 s, int pass, int P, int me) {
-#pragma unroll 1
-            for (int k = 0; k < 4; ++k) {
-                int fa, fb, fc;
-                face_of(s, k, fa, fb, fc);
-                const uint32_t h = face_hash(fa, fb, fc);
-                if (P == 1 || (int)(((h & 0xFFFFu) * (uint32_t)P) >> 16) == pass)
-                    visit(ins_tag, h, fa, fb, fc, me, k);
-            }
-        };
         using Ins = std::integral_constant<bool, true>;
         using Look = std::integral_constant<bool, false>;
 
@@ -405,17 +376,72 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
         }
         __syncthreads();
         auto is_low = [&](int v) -> uint32_t { return (lowb[v >> 5] >> (v & 31)) & 1u; };
-        // the faces of a tetrahedron outside the rows worth looking up
-        auto look = [&](int4 s, int pass, int P, int me) {
-            const uint32_t lm = is_low(s.x) | is_low(s.y) << 1 | is_low(s.z) << 2 | is_low(s.w) << 3;
-#pragma unroll 1
-            for (int k = 0; k < 4; ++k) {
-                if (lm & ~(1u << k)) continue;  // a vertex of face k is in a lower cluster
-                int fa, fb, fc;
-                face_of(s, k, fa, fb, fc);
-                const uint32_t h = face_hash(fa, fb, fc);
-                if (P == 1 || (int)(((h & 0xFFFFu) * (uint32_t)P) >> 16) == pass)
-                    visit(Look{}, h, fa, fb, fc, me, k);
+
+        // Each lane takes stream positions p0 + tid, p0 + tid + B, ... below
+        // p1.  The four faces of its tetrahedron are hashed together; then the
+        // lane works through the faces to visit (those of this pass; for
+        // lookups, those with no vertex in a lower cluster) one probe step
+        // (linear probing) per iteration, going on to its next face as soon as
+        // one is done, so the wave waits for the lane with the most steps over
+        // four faces rather than for the longest chain of each face in turn.
+        // kIns: enter the faces (internal tetrahedra) or only look them up.
+        auto stream_faces = [&](auto ins_tag, int p0, int p1, int pass, int P) {
+            constexpr bool kIns = decltype(ins_tag)::value;
+            for (int p = p0 + tid; p < p1; p += B) {
+                int4 s;
+                uint32_t todo;
+                if constexpr (kIns) {
+                    s = tet(p);
+                    todo = 0xFu;
+                } else {
+                    s = tet_global(p);
+                    // one lower vertex: only the face without it; two or more: none
+                    const uint32_t lm = is_low(s.x) | is_low(s.y) << 1 | is_low(s.z) << 2 | is_low(s.w) << 3;
+                    todo = lm == 0u ? 0xFu : (__popc(lm) > 1 ? 0u : lm);
+                }
+                uint32_t h4[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    int a0, b0, c0;
+                    face_of(s, k, a0, b0, c0);
+                    h4[k] = face_hash(a0, b0, c0);
+                    if (P > 1 && (int)(((h4[k] & 0xFFFFu) * (uint32_t)P) >> 16) != pass) todo &= ~(1u << k);
+                }
+                int k = 0, fa = 0, fb = 0, fc = 0, left = 0;
+                uint32_t idx = 0u;
+                auto start = [&]() {
+                    k = __ffs(todo) - 1;
+                    face_of(s, k, fa, fb, fc);
+                    const uint32_t h = k == 0 ? h4[0] : k == 1 ? h4[1] : k == 2 ? h4[2] : h4[3];
+                    idx = (uint32_t)(((unsigned long long)h * (uint32_t)H) >> 32);
+                    left = H + 2;  // a failed swap re-reads its cell; each cell changes once
+                };
+                if (todo) start();
+                while (todo) {
+                    uint32_t w;
+                    const uint32_t c = CL::read(ht, idx, w);
+                    const int q = c == 0u ? 0 : (int)c - 1;
+                    // the holder's face that is {fa, fb, fc}, if any (a tetrahedron
+                    // meets its own earlier faces on the way: skip them)
+                    const int kq = face_index(tet(q), fa, fb, fc);
+                    const bool hit = c != 0u && q != p && kq >= 0;
+                    bool stop = hit || (c == 0u && !kIns);
+                    if (kIns && c == 0u) stop = CL::try_set(ht, idx, w, (uint32_t)p + 1u);
+                    if (hit) {
+                        bool bad = CL::mark(win, 4 * (uint32_t)q + kq, (uint32_t)p + 1u);
+                        if (kIns) bad |= CL::mark(win, 4 * (uint32_t)p + k, c);
+                        if (bad) s_fail = 1;
+                    }
+                    if (c != 0u && !hit) idx = idx + 1 == (uint32_t)H ? 0u : idx + 1;
+                    if (--left == 0 && !stop) {
+                        if (kIns) s_full = 1;
+                        stop = true;
+                    }
+                    if (stop) {
+                        todo &= todo - 1u;
+                        if (todo) start();
+                    }
+                }
             }
         };
 
@@ -425,11 +451,11 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
             for (int pass = 0; pass < P; ++pass) {
                 for (int i = tid; i < ht_words; i += B) ht32[i] = 0u;
                 __syncthreads();
-                for (int p = tid; p < nT; p += B) faces(Ins{}, tet(p), pass, P, p);
+                stream_faces(Ins{}, 0, nT, pass, P);
                 __syncthreads();
                 PHASE_MARK(7);
                 if (s_full) break;
-                for (int p = nT + tid; p < ntot; p += B) look(tet_global(p), pass, P, p);
+                stream_faces(Look{}, nT, ntot, pass, P);
                 __syncthreads();
                 PHASE_MARK(8);
             }
