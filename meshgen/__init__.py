@@ -29,6 +29,8 @@ from __future__ import annotations
 import math
 from dataclasses import dataclass, field
 
+import os
+
 import numpy as np
 
 __all__ = [
@@ -84,11 +86,12 @@ def kuhn_grid(n: int):
     k, j, i = np.meshgrid(ax, ax, ax, indexing="ij")
     coords = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1)
     m = n - 1
-    c = np.arange(m, dtype=np.int64)
+    it = np.int64 if n ** 3 >= 2 ** 31 else np.int32
+    c = np.arange(m, dtype=it)
     ck, cj, ci = np.meshgrid(c, c, c, indexing="ij")
     p0 = (ci + n * (cj + n * ck)).ravel()
     step = (1, n, n * n)
-    tets = np.empty((p0.shape[0], 6, 4), dtype=np.int64)
+    tets = np.empty((p0.shape[0], 6, 4), dtype=it)
     for o, (a, b, _c) in enumerate(_AXIS_ORDERS):
         tets[:, o, 0] = p0
         tets[:, o, 1] = p0 + step[a]
@@ -167,6 +170,36 @@ def clusters_lognormal(coords: np.ndarray, median: float, sigma: float, lo: int,
 # Refinement by centroid insertion
 # ----------------------------------------------------------------------------
 
+def _blob_weights(coords: np.ndarray, tets: np.ndarray, mu: np.ndarray, s: np.ndarray,
+                  chunk: int = 1 << 20) -> np.ndarray:
+    """w[t] = sum_b exp(-|x_t - mu_b|^2 / (2 s_b^2)) at the centroid x_t of each
+    tetrahedron, in chunks over threads (numpy releases the GIL); the same
+    operations in the same order as a whole-array evaluation, so the same bits."""
+    from concurrent.futures import ThreadPoolExecutor
+    nt = tets.shape[0]
+    w = np.zeros(nt, dtype=np.float64)
+
+    def work(lo):
+        hi = min(nt, lo + chunk)
+        t = tets[lo:hi]
+        cen = np.zeros((hi - lo, 3), dtype=np.float64)
+        for q in range(4):
+            cen += coords[t[:, q]]
+        cen *= 0.25
+        acc = np.zeros(hi - lo, dtype=np.float64)
+        for b in range(mu.shape[0]):
+            d = cen - mu[b]
+            d *= d
+            d2 = d[:, 0] + d[:, 1]
+            d2 += d[:, 2]
+            acc += np.exp(-d2 / (2.0 * s[b] * s[b]))
+        w[lo:hi] = acc
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(work, range(0, nt, chunk)))
+    return w
+
+
 def refine(coords: np.ndarray, tets: np.ndarray, n: int, frac: float, rounds: int,
            rng: np.random.Generator, nblobs: int = 8):
     """Rounds of 1-to-4 centroid splits concentrated in Gaussian blobs.
@@ -188,15 +221,7 @@ def refine(coords: np.ndarray, tets: np.ndarray, n: int, frac: float, rounds: in
         nt = tets.shape[0]
         u = rng.uniform(0.0, 1.0, size=nt)
         k = int(round(frac * nt))
-        cen = np.zeros((nt, 3), dtype=np.float64)
-        for q in range(4):
-            cen += coords[tets[:, q]]
-        cen *= 0.25
-        w = np.zeros(nt, dtype=np.float64)
-        for b in range(nblobs):
-            d2 = ((cen - mu[b]) ** 2).sum(axis=1)
-            w += np.exp(-d2 / (2.0 * s[b] * s[b]))
-        del cen
+        w = _blob_weights(coords, tets, mu, s)
         with np.errstate(divide="ignore"):
             key = np.log(np.maximum(u, 1e-300)) / np.maximum(w, 1e-300)
         sel = np.argpartition(-key, k - 1)[:k] if k > 0 else np.empty(0, dtype=np.int64)
@@ -228,7 +253,16 @@ def _permute(rng: np.random.Generator, tets, cluster, coords, scalar):
     vperm = rng.permutation(nv).astype(np.int32)
     tperm = rng.permutation(nt)
     new_tets = np.empty_like(tets)
-    new_tets[tperm] = vperm[tets]
+    # new_tets[tperm] = vperm[tets], in chunks over threads
+    from concurrent.futures import ThreadPoolExecutor
+    chunk = 1 << 21
+
+    def work(lo):
+        hi = min(nt, lo + chunk)
+        new_tets[tperm[lo:hi]] = vperm[tets[lo:hi]]
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(work, range(0, nt, chunk)))
     new_cl = np.empty_like(cluster)
     new_cl[vperm] = cluster
     new_coords = None

@@ -197,9 +197,12 @@ __device__ __forceinline__ void sort32(uint32_t (&v)[32]) {
 //   read     the cell and the word holding it;
 //   try_set  an empty cell, by compare-and-swap of its word against the word
 //            read (fails when the word changed: read again);
-//   mark     a partner cell by atomic OR; true when it was already set.  A
-//            second mark means a third tetrahedron on one face, after which
-//            the windows are discarded, so what the OR leaves does not matter.
+//   mark     a partner cell by atomic OR; true when it already held another
+//            tetrahedron, which means a third tetrahedron on one face (the
+//            windows are then discarded, so what the OR leaves does not
+//            matter).  The same pair can be marked twice: a face of t is found
+//            through t's record of another face, and later t finds its partner
+//            through one of the partner's records; that is not a conflict.
 template <bool kL>
 struct Cells;
 template <>
@@ -215,7 +218,8 @@ struct Cells<true> {
     }
     __device__ static bool mark(T *a, uint32_t i, uint32_t v) {
         const int sh = (i & 1) * 16;
-        return ((atomicOr(word(a, i), v << sh) >> sh) & 0xFFFFu) != 0u;
+        const uint32_t old = (atomicOr(word(a, i), v << sh) >> sh) & 0xFFFFu;
+        return old != 0u && old != v;
     }
     __device__ static uint32_t get(const T *a, uint32_t i) { return a[i]; }
 };
@@ -227,7 +231,10 @@ struct Cells<false> {
         return w;
     }
     __device__ static bool try_set(T *a, uint32_t i, uint32_t w, uint32_t v) { return atomicCAS(a + i, w, v) == w; }
-    __device__ static bool mark(T *a, uint32_t i, uint32_t v) { return atomicOr(a + i, v) != 0u; }
+    __device__ static bool mark(T *a, uint32_t i, uint32_t v) {
+        const uint32_t old = atomicOr(a + i, v);
+        return old != 0u && old != v;
+    }
     __device__ static uint32_t get(const T *a, uint32_t i) { return a[i]; }
 };
 
@@ -646,10 +653,10 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
         PHASE_MARK(3);
         // ---- VV: one row per group of G lanes (16 or 32), in rounds of B/G
         // rows.  The group marks the row's neighbours in its bitmap over the
-        // local table (the lanes that set a bit count the distinct ones); the
-        // round's counts give every row its offset after one barrier; the row
-        // is then read from the bitmap in word order, which is original id
-        // order, each lane taking a run of consecutive words.
+        // local table; each lane takes a run of consecutive words (into
+        // registers when they are few) and counts their bits; the round's
+        // counts give every row its offset after one barrier; the row is then
+        // emitted in word order, which is original id order.
         if ((mask & kRelVV) && vt_ok) {
             __shared__ int s_vc[2][B / 16];
             const int W = pl.W;
@@ -667,26 +674,46 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
             auto rows_by = [&](auto gtag) {
                 constexpr int G = decltype(gtag)::value;
                 constexpr int NG = B / G;
+                constexpr int KMAX = 8;  // bitmap words a lane keeps in registers
                 const int grp = tid / G, gl = tid % G;
                 uint32_t *wb = wbm + (int64_t)grp * W;
                 const int K = (W + G - 1) / G;  // words per lane
                 const int wbeg = gl * K, wend = min(W, wbeg + K);
-                auto mark = [&](int v, int self) -> int {
-                    if (v == self) return 0;
-                    const uint32_t bit = 1u << (v & 31);
-                    return (atomicOr(&wb[v >> 5], bit) & bit) == 0u ? 1 : 0;
+                const bool in_regs = K <= KMAX;
+                auto mark = [&](int v, int self) {
+                    if (v != self) atomicOr(&wb[v >> 5], 1u << (v & 31));
                 };
                 int par = 0;
                 for (int r0 = 0; r0 < nV; r0 += NG) {
                     const int r = r0 + grp;
-                    int c = 0;
                     if (r < nV) {
                         const int self = rowl[r];
                         for (int i = cnt[r] + gl; i < cnt[r + 1]; i += G) {
                             const int4 t = tet(lvt[i]);
-                            c += mark(t.x, self) + mark(t.y, self) + mark(t.z, self) + mark(t.w, self);
+                            mark(t.x, self);
+                            mark(t.y, self);
+                            mark(t.z, self);
+                            mark(t.w, self);
                         }
                     }
+                    wave_fence();
+                    // this lane's run of words: into registers (and cleared), counted
+                    uint32_t wv[KMAX];
+                    int n = 0;
+                    if (in_regs) {
+#pragma unroll
+                        for (int j = 0; j < KMAX; ++j) {
+                            const int w = wbeg + j;
+                            wv[j] = w < wend ? wb[w] : 0u;
+                            n += __popc(wv[j]);
+                        }
+#pragma unroll
+                        for (int j = 0; j < KMAX; ++j)
+                            if (wv[j]) wb[wbeg + j] = 0u;
+                    } else {
+                        for (int w = wbeg; w < wend; ++w) n += __popc(wb[w]);
+                    }
+                    int c = n;
 #pragma unroll
                     for (int d = G / 2; d >= 1; d >>= 1) c += __shfl_xor(c, d, G);
                     if (gl == 0) s_vc[par][grp] = c;
@@ -706,8 +733,6 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
                     if (r < nV) {
                         if (gl == 0) blk[lay.vv_off + r] = o_row;
                         const bool fits = o_row + c <= cap;
-                        int n = 0;
-                        for (int w = wbeg; w < wend; ++w) n += __popc(wb[w]);
                         int y = n;
 #pragma unroll
                         for (int d = 1; d < G; d <<= 1) {
@@ -715,16 +740,29 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
                             if (gl >= d) y += z;
                         }
                         int pos = o_row + y - n;
-                        for (int w = wbeg; w < wend; ++w) {
-                            uint32_t bits = wb[w];
-                            if (bits) {
-                                wb[w] = 0u;
-                                if (fits) {
-                                    while (bits) {
-                                        const int b = __ffs(bits) - 1;
-                                        bits &= bits - 1u;
-                                        blk[lay.vv_ent + pos] = orig(w * 32 + b);
-                                        ++pos;
+                        if (in_regs) {
+#pragma unroll
+                            for (int j = 0; j < KMAX; ++j) {
+                                uint32_t bits = fits ? wv[j] : 0u;
+                                while (bits) {
+                                    const int b = __ffs(bits) - 1;
+                                    bits &= bits - 1u;
+                                    blk[lay.vv_ent + pos] = orig((wbeg + j) * 32 + b);
+                                    ++pos;
+                                }
+                            }
+                        } else {
+                            for (int w = wbeg; w < wend; ++w) {
+                                uint32_t bits = wb[w];
+                                if (bits) {
+                                    wb[w] = 0u;
+                                    if (fits) {
+                                        while (bits) {
+                                            const int b = __ffs(bits) - 1;
+                                            bits &= bits - 1u;
+                                            blk[lay.vv_ent + pos] = orig(w * 32 + b);
+                                            ++pos;
+                                        }
                                     }
                                 }
                             }

@@ -154,6 +154,7 @@ def test_config2_sampled_and_totals():
                     if not all(np.array_equal(g, e) for g, e in zip(got, exp)):
                         bad.append((k, rel))
         assert tt_rows == m.nt
+        assert ctx.stats()["tt_exhaustive_blocks"] == 0
         ctx.release(tk)
         assert not bad, bad
 
@@ -234,3 +235,42 @@ def test_refined_lognormal_clusters():
             compare_all(ctx, m, orc)
             st = ctx.stats()
             _say(form, "global-path blocks", st["global_path_blocks"], "exhaustive TT", st["tt_exhaustive_blocks"])
+            # every face is shared by at most two tetrahedra here: the face
+            # table pairs all of them (no fallback to exhaustive pairing)
+            assert st["tt_exhaustive_blocks"] == 0
+
+
+def test_refined_256_full_size_sampled():
+    """The 256^3 lattice refined in Gaussian blobs (34M vertices, 151M
+    tetrahedra, 40,579 lognormal clusters of 64..8192 vertices) built in one
+    batched launch; a seeded sample of clusters plus the four largest compared
+    with the oracle; no block needs the exhaustive TT pairing."""
+    gale = _gale()
+    m = meshgen.config(3)
+    _say("256^3 refined", m.nv, m.nt, m.nclusters)
+    sizes = np.bincount(m.cluster, minlength=m.nclusters)
+    with gale.Context(form="batched") as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        _say("loaded")
+        tk = ctx.build(np.arange(m.nclusters, dtype=np.int32), 7, "batched")
+        ctx.poll(tk)
+        st = ctx.stats()
+        _say("built", st["entries_built"], "global-path blocks", st["global_path_blocks"],
+             "exhaustive", st["tt_exhaustive_blocks"])
+        assert st["tt_exhaustive_blocks"] == 0
+        ctx.release(tk)
+        rng = np.random.default_rng(31)
+        sample = sorted(set(rng.choice(m.nclusters, 20, replace=False).tolist())
+                        | set(np.argsort(-sizes)[:4].tolist()) | {0, m.nclusters - 1})
+        orc = oracle.Oracle.of(m)
+        _say("oracle ready")
+        tk = ctx.submit(np.array(sample, np.int32), 7)
+        bad = []
+        for k in sample:
+            for rel in REL:
+                got = ctx.block(tk, int(k), rel)
+                exp = orc.block(int(k), rel)
+                if not all(np.array_equal(g, e) for g, e in zip(got, exp)):
+                    bad.append((int(k), rel))
+        ctx.release(tk)
+    assert not bad, bad
