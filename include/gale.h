@@ -74,7 +74,10 @@ typedef struct {
     int32_t  max_inflight;        /* SERVE: batches on the GPU at once (1..8); 0 = 2 */
     uint64_t cache_budget_bytes;  /* SERVE: bytes of device memory for resident blocks; 0 = 1 GiB */
     int32_t  max_queue;           /* SERVE: pending requests accepted before EAGAIN; 0 = 65536 */
-    int32_t  reserved;
+    int32_t  launch_classes;      /* BATCHED form: which workgroup shapes clusters may use, bit 0 = 1024 threads with
+                                     the whole LDS, bit 1 = 512 threads with half, bit 2 = 256 threads with a
+                                     quarter (several workgroups per CU); each cluster takes the smallest shape its
+                                     working set fits.  0 = the 1024-thread shape only. */
     void    *hip_stream;          /* borrowed hipStream_t for DIRECT mode work, or NULL for a library-owned stream.
                                      Must outlive the context. */
 } gale_config;
@@ -155,6 +158,37 @@ gale_status gale_submit(gale_ctx *ctx, const int32_t *cluster_ids, int32_t n, ui
  * with gale_block_device after gale_poll reports it ready.  DIRECT mode only. */
 gale_status gale_build(gale_ctx *ctx, const int32_t *cluster_ids, int32_t n, uint32_t rel_mask,
                        int32_t form, uint64_t *ticket_out);
+
+/* Choose the workgroup shapes for batched work by measurement (batch
+ * formation with cluster buckets; Section 4.5 batches every pending request,
+ * these buckets decide how each cluster of a batch runs).  Each candidate
+ * value of gale_config.launch_classes (0, 2, 4, 6) builds the clusters
+ * ids[0..n) with rel_mask in the BATCHED form, device only, once to warm up
+ * and then `reps` times; the one with the shortest mean kernel time is kept
+ * for the context's later batched work.  DIRECT mode with a mesh loaded; no
+ * other call may use the context meanwhile.  chosen_out (may be NULL)
+ * receives the chosen value, ms_out (may be NULL; 4 doubles) the mean
+ * milliseconds of each candidate in the order above.  EINVAL, ESTATE,
+ * EDEVICE as gale_build. */
+gale_status gale_autotune(gale_ctx *ctx, const int32_t *cluster_ids, int32_t n, uint32_t rel_mask, int32_t reps,
+                          int32_t *chosen_out, double *ms_out);
+
+/* hipGraph-captured submit for a request built again and again (the same
+ * clusters and relations, e.g. every step of an iterative analysis).
+ * gale_graph_create lays the request's blocks out in one device buffer, copies
+ * its work list to the device and captures its launches (queue reset and the
+ * persistent kernels of every workgroup shape) in a HIP graph; DIRECT mode.
+ * gale_graph_launch replays the graph on the context stream and returns a
+ * ticket read with gale_poll and gale_block_device and freed with
+ * gale_release; all tickets of one graph share its buffer, so a ticket's
+ * blocks are valid until the next gale_graph_launch of the same graph.
+ * gale_graph_destroy waits for the context stream and frees the graph and its
+ * buffer (its tickets must be released first).  EINVAL, ESTATE, ENOENT
+ * (unknown graph), ENOMEM, EDEVICE. */
+gale_status gale_graph_create(gale_ctx *ctx, const int32_t *cluster_ids, int32_t n, uint32_t rel_mask,
+                              uint64_t *graph_out);
+gale_status gale_graph_launch(gale_ctx *ctx, uint64_t graph, uint64_t *ticket_out);
+gale_status gale_graph_destroy(gale_ctx *ctx, uint64_t graph);
 
 /* Wait up to timeout_ns (0 = just test, <0 = forever) for the ticket.
  * OK = ready; EAGAIN = not yet; ENOENT = unknown ticket. */

@@ -97,15 +97,43 @@ int64_t lay_out_items(const gale_ctx *ctx, std::vector<WorkItem> &items, int64_t
     return w - out_base_word;
 }
 
-bool item_on_lds_path(const gale_ctx *ctx, const WorkItem &it) {
-    return lds_plan(ctx->meta[it.cluster], it.mask, ctx->lds_budget, ctx->block_threads).ok != 0;
+// Launch classes: the configured shape with the whole budget, then the
+// smaller shapes the mask enables (half and a quarter of the LDS).
+void setup_classes(gale_ctx *ctx, int mask) {
+    ctx->classes.clear();
+    ctx->classes.push_back({ctx->block_threads, ctx->lds_budget, ctx->grid_lds});
+    const struct {
+        int bit, bt, div;
+    } shapes[] = {{2, 512, 2}, {4, 256, 4}};
+    for (const auto &sh : shapes) {
+        if (!(mask & sh.bit)) continue;
+        int64_t b = ctx->shared_per_block / sh.div - ctx->static_lds;
+        b = std::min<int64_t>(b, ctx->lds_budget);
+        if (b < 4096) continue;
+        int o = 0;
+        if (persistent_occupancy(sh.bt, true, (size_t)b, &o) != hipSuccess || o <= 0) o = 1;
+        ctx->classes.push_back({sh.bt, b, ctx->num_cus * o});
+    }
+    ctx->class_mask = mask;
 }
+
+// The workgroup shape of an item: the smallest (last) launch class whose LDS
+// plan fits, or -1 for the global-workspace path.
+int item_class(const gale_ctx *ctx, const WorkItem &it) {
+    for (int c = (int)ctx->classes.size() - 1; c >= 0; --c) {
+        const gale_ctx::LaunchClass &lc = ctx->classes[c];
+        if (lds_plan(ctx->meta[it.cluster], it.mask, lc.budget, lc.bt).ok) return c;
+    }
+    return -1;
+}
+
+bool item_on_lds_path(const gale_ctx *ctx, const WorkItem &it) { return item_class(ctx, it) >= 0; }
 
 int64_t workspace_bytes(const gale_ctx *ctx, const std::vector<WorkItem> &items, int *n_global) {
     int64_t need = 0;
     int ng = 0;
     for (const WorkItem &it : items) {
-        if (!item_on_lds_path(ctx, it)) {
+        if (item_class(ctx, it) < 0) {
             const Plan gp = ws_plan(ctx->meta[it.cluster], it.mask, ctx->block_threads);
             need = std::max<int64_t>(need, gp.bytes);
             ++ng;
@@ -132,67 +160,114 @@ void destroy_ticket_events(Ticket *t) {
     }
 }
 
-// Launch items already uploaded in launch order: the first n_lds take the
-// LDS path, the next n_glob the global-workspace path.  PLAIN: one launch per
-// item; BATCHED: one persistent launch per path, each with its own queue word.
+// Launch items already uploaded in launch order: first the items of launch
+// class 0, then class 1, ... (ncls[c] each), then the n_glob items of the
+// global-workspace path.  PLAIN: one launch per item; BATCHED: one persistent
+// launch per class and one for the global path, each with its own queue word
+// (d_queue[c], d_queue[classes]).  fork: run the launches on the auxiliary
+// streams, forked from and joined back into st (DIRECT mode); otherwise one
+// after another on st.  kev, when given, brackets all of them on st.
 gale_status launch_batch(gale_ctx *ctx, int form, int32_t *d_out, int32_t *d_hdr, const WorkItem *d_items,
-                         int n_lds, int n_glob, int32_t *d_queue, char *d_ws, int64_t ws_stride, hipStream_t st,
-                         const hipEvent_t *kev, bool *kev_recorded) {
+                         const std::vector<int> &ncls, int n_glob, int32_t *d_queue, char *d_ws, int64_t ws_stride,
+                         hipStream_t st, bool fork, const hipEvent_t *kev, bool *kev_recorded) {
     KArgs a = base_args(ctx);
     a.out = d_out;
     a.hdr = d_hdr;
     a.ws = d_ws;
     a.ws_stride = ws_stride;
     hipError_t e = hipSuccess;
+    const int ncl = (int)ctx->classes.size();
     if (form == GALE_FORM_PLAIN) {
-        for (int i = 0; i < n_lds + n_glob && e == hipSuccess; ++i) {
+        int i = 0;
+        for (int c = 0; c < ncl && e == hipSuccess; ++c) {
+            const gale_ctx::LaunchClass &lc = ctx->classes[c];
+            a.lds_budget = (int32_t)lc.budget;
+            for (int j = 0; j < ncls[c] && e == hipSuccess; ++j, ++i) {
+                a.items = d_items + i;
+                a.nitems = 1;
+                e = launch_items(a, true, lc.bt, 1, (size_t)lc.budget, st);
+                ctx->n_launches++;
+            }
+        }
+        a.lds_budget = (int32_t)ctx->lds_budget;
+        for (int j = 0; j < n_glob && e == hipSuccess; ++j, ++i) {
             a.items = d_items + i;
             a.nitems = 1;
-            e = launch_items(a, i < n_lds, ctx->block_threads, 1, ctx->lds_budget, st);
+            e = launch_items(a, false, ctx->block_threads, 1, 0, st);
             ctx->n_launches++;
         }
     } else {
-        if (n_lds > 0) {
-            a.items = d_items;
-            a.nitems = n_lds;
-            a.queue = d_queue;
-            if (kev) e = hipEventRecord(kev[0], st);
-            if (e == hipSuccess)
-                e = launch_persistent(a, true, ctx->block_threads, std::min<int>(n_lds, ctx->grid_lds),
-                                      ctx->lds_budget, st);
-            if (kev && e == hipSuccess) e = hipEventRecord(kev[1], st);
-            if (kev && kev_recorded && e == hipSuccess) *kev_recorded = true;
-            ctx->n_launches++;
+        // the launches to make: (class or -1, first item, count)
+        struct L {
+            int c, first, n;
+        };
+        std::vector<L> ls;
+        int first = 0;
+        for (int c = 0; c < ncl; ++c) {
+            if (ncls[c] > 0) ls.push_back({c, first, ncls[c]});
+            first += ncls[c];
         }
-        if (n_glob > 0 && e == hipSuccess) {
-            a.items = d_items + n_lds;
-            a.nitems = n_glob;
-            a.queue = d_queue + 1;
-            e = launch_persistent(a, false, ctx->block_threads, std::min<int>(n_glob, ctx->grid_glob), 0, st);
+        if (n_glob > 0) ls.push_back({-1, first, n_glob});
+        const bool use_aux = fork && ls.size() > 1 && ctx->aux.size() >= ls.size() - 1;
+        if (kev) e = hipEventRecord(kev[0], st);
+        if (use_aux && e == hipSuccess) e = hipEventRecord(ctx->fork_ev, st);
+        for (size_t li = 0; li < ls.size() && e == hipSuccess; ++li) {
+            const L &l = ls[li];
+            hipStream_t s2 = st;
+            if (use_aux && li > 0) {
+                s2 = ctx->aux[li - 1];
+                e = hipStreamWaitEvent(s2, ctx->fork_ev, 0);
+                if (e != hipSuccess) break;
+            }
+            a.items = d_items + l.first;
+            a.nitems = l.n;
+            a.queue = d_queue + (l.c >= 0 ? l.c : ncl);
+            if (l.c >= 0) {
+                const gale_ctx::LaunchClass &lc = ctx->classes[l.c];
+                a.lds_budget = (int32_t)lc.budget;
+                e = launch_persistent(a, true, lc.bt, std::min<int>(l.n, lc.grid), (size_t)lc.budget, s2);
+            } else {
+                a.lds_budget = (int32_t)ctx->lds_budget;
+                e = launch_persistent(a, false, ctx->block_threads, std::min<int>(l.n, ctx->grid_glob), 0, s2);
+            }
             ctx->n_launches++;
+            if (e == hipSuccess && use_aux && li > 0) {
+                e = hipEventRecord(ctx->join_ev[li - 1], s2);
+                if (e == hipSuccess) e = hipStreamWaitEvent(st, ctx->join_ev[li - 1], 0);
+            }
         }
+        if (kev && e == hipSuccess) e = hipEventRecord(kev[1], st);
+        if (kev && kev_recorded && e == hipSuccess) *kev_recorded = true;
     }
     if (e != hipSuccess) return fail(GALE_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     return GALE_OK;
 }
 
-// Upload items (layout order in `items`, with out_word and hdr_index set) in
-// launch order with two zero queue words, and launch.  Buffers come from the
-// pools; the caller releases them.
-gale_status upload_and_launch(gale_ctx *ctx, int form, const std::vector<WorkItem> &items, int32_t *d_out,
-                              Buf *&dev_items, Buf *&dev_hdr, Buf *&host_items, Buf *&ws, hipStream_t st,
-                              const hipEvent_t *kev, bool *kev_recorded) {
+// Order items by launch class (then the global path), acquire the work-list
+// buffers and copy the list with zeroed queue words to the device.
+gale_status stage_items(gale_ctx *ctx, int form, const std::vector<WorkItem> &items, Buf *&dev_items,
+                        Buf *&dev_hdr, Buf *&host_items, Buf *&ws, hipStream_t st, std::vector<int> &ncls,
+                        int &n_glob, int64_t &wsb) {
     hipError_t e;
     const int n = (int)items.size();
+    const int ncl = (int)ctx->classes.size();
+    std::vector<int> cls(n);
+    ncls.assign(ncl, 0);
+    for (int i = 0; i < n; ++i) {
+        cls[i] = item_class(ctx, items[i]);
+        if (cls[i] >= 0) ncls[cls[i]]++;
+    }
     std::vector<WorkItem> order;
     order.reserve(n);
-    for (const WorkItem &it : items)
-        if (item_on_lds_path(ctx, it)) order.push_back(it);
-    const int n_lds = (int)order.size();
-    for (const WorkItem &it : items)
-        if (!item_on_lds_path(ctx, it)) order.push_back(it);
-    const int n_glob = n - n_lds;
-    const int64_t wsb = workspace_bytes(ctx, items, nullptr);
+    for (int c = 0; c < ncl; ++c)
+        for (int i = 0; i < n; ++i)
+            if (cls[i] == c) order.push_back(items[i]);
+    std::vector<WorkItem> glob;
+    for (int i = 0; i < n; ++i)
+        if (cls[i] < 0) glob.push_back(items[i]);
+    n_glob = (int)glob.size();
+    order.insert(order.end(), glob.begin(), glob.end());
+    wsb = workspace_bytes(ctx, glob, nullptr);
     ctx->n_global_blocks += n_glob;
     const int slots = form == GALE_FORM_PLAIN ? 1 : std::min<int>(std::max(n_glob, 1), ctx->grid_glob);
     dev_items = ctx->dev_pool.acquire((size_t)n * sizeof(WorkItem) + 64, &e);
@@ -204,13 +279,27 @@ gale_status upload_and_launch(gale_ctx *ctx, int form, const std::vector<WorkIte
         if (!ws) return fail(GALE_ENOMEM, "workspace");
     }
     char *hi = (char *)host_items->ptr;
-    std::memset(hi, 0, 64);
+    std::memset(hi, 0, 64);  // the queue words, one per class and one for the global path
     std::memcpy(hi + 64, order.data(), (size_t)n * sizeof(WorkItem));
     e = hipMemcpyAsync(dev_items->ptr, hi, (size_t)n * sizeof(WorkItem) + 64, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return fail(GALE_EDEVICE, std::string("work list copy: ") + hipGetErrorString(e));
+    return GALE_OK;
+}
+
+// Stage items (layout order in `items`, with out_word and hdr_index set) and
+// launch them.  Buffers come from the pools; the caller releases them.
+gale_status upload_and_launch(gale_ctx *ctx, int form, const std::vector<WorkItem> &items, int32_t *d_out,
+                              Buf *&dev_items, Buf *&dev_hdr, Buf *&host_items, Buf *&ws, hipStream_t st,
+                              const hipEvent_t *kev, bool *kev_recorded) {
+    std::vector<int> ncls;
+    int n_glob = 0;
+    int64_t wsb = 0;
+    gale_status s = stage_items(ctx, form, items, dev_items, dev_hdr, host_items, ws, st, ncls, n_glob, wsb);
+    if (s) return s;
     char *di = (char *)dev_items->ptr;
-    return launch_batch(ctx, form, d_out, (int32_t *)dev_hdr->ptr, (const WorkItem *)(di + 64), n_lds, n_glob,
-                        (int32_t *)di, ws ? (char *)ws->ptr : nullptr, wsb, st, kev, kev_recorded);
+    return launch_batch(ctx, form, d_out, (int32_t *)dev_hdr->ptr, (const WorkItem *)(di + 64), ncls, n_glob,
+                        (int32_t *)di, ws ? (char *)ws->ptr : nullptr, wsb, st, ctx->cfg.mode == GALE_MODE_DIRECT,
+                        kev, kev_recorded);
 }
 
 // Lay out the batch's items in a fresh output buffer and launch them.
@@ -228,6 +317,10 @@ gale_status run_items(gale_ctx *ctx, Batch &b, int form, hipStream_t st) {
 }
 
 void release_batch(gale_ctx *ctx, Batch &b) {
+    if (b.borrowed) {  // a graph ticket: the buffers belong to the prepared request
+        b.out = b.dev_items = b.dev_hdr = b.ws = b.host_items = b.host_hdr = b.host_out = nullptr;
+        return;
+    }
     ctx->dev_pool.release(b.out);
     ctx->dev_pool.release(b.dev_items);
     ctx->dev_pool.release(b.dev_hdr);
@@ -470,6 +563,124 @@ gale_status direct_build(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t 
     return GALE_OK;
 }
 
+// ---- prepared (graph) requests --------------------------------------------
+gale_status graph_create(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t mask, uint64_t *out) {
+    gale_status s = check_request(ctx, ids, n, mask);
+    if (s) return s;
+    if (ctx->poisoned) return fail(GALE_EDEVICE, "context poisoned by an earlier device error");
+    auto *g = new Prepared();
+    g->batch.items = make_items(ctx, ids, n, mask, GALE_FORM_BATCHED);
+    g->mask = mask;
+    for (size_t i = 0; i < g->batch.items.size(); ++i) g->by_cluster[g->batch.items[i].cluster].push_back((int)i);
+    std::lock_guard<std::mutex> lk(ctx->direct_mu);
+    Batch &b = g->batch;
+    hipError_t e = hipSuccess;
+    const int ni = (int)b.items.size();
+    b.out_words = lay_out_items(ctx, b.items, 0);
+    b.out = ctx->dev_pool.acquire((size_t)b.out_words * 4 + 256, &e);
+    b.host_hdr = ctx->pin_pool.acquire((size_t)ni * 32 + 64, &e);
+    if (!b.out || !b.host_hdr) s = fail(GALE_ENOMEM, "prepared request buffers");
+    std::vector<int> ncls;
+    int n_glob = 0;
+    int64_t wsb = 0;
+    if (!s && ni > 0)
+        s = stage_items(ctx, GALE_FORM_BATCHED, b.items, b.dev_items, b.dev_hdr, b.host_items, b.ws, ctx->stream,
+                        ncls, n_glob, wsb);
+    if (!s && hipStreamSynchronize(ctx->stream) != hipSuccess) s = fail(GALE_EDEVICE, "work list copy");
+    if (!s && ni > 0) {
+        // capture: zero the queue words, then the launches (forked over the
+        // auxiliary streams and joined back)
+        e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) e = launch_zero((int32_t *)b.dev_items->ptr, 16, ctx->stream);
+        gale_status ls = GALE_OK;
+        if (e == hipSuccess) {
+            char *di = (char *)b.dev_items->ptr;
+            ls = launch_batch(ctx, GALE_FORM_BATCHED, (int32_t *)b.out->ptr, (int32_t *)b.dev_hdr->ptr,
+                              (const WorkItem *)(di + 64), ncls, n_glob, (int32_t *)di,
+                              b.ws ? (char *)b.ws->ptr : nullptr, wsb, ctx->stream, true, nullptr, nullptr);
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(ctx->stream, &graph);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess && ls == GALE_OK) e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+        g->graph = graph;
+        if (ls) s = ls;
+        else if (e != hipSuccess) s = fail(GALE_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    if (s) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        release_batch(ctx, b);
+        delete g;
+        return s;
+    }
+    *out = ++ctx->next_graph;
+    ctx->graphs[*out] = g;
+    return GALE_OK;
+}
+
+gale_status graph_launch(gale_ctx *ctx, uint64_t gid, uint64_t *ticket_out) {
+    if (ctx->poisoned) return fail(GALE_EDEVICE, "context poisoned by an earlier device error");
+    auto *t = new Ticket();
+    {
+        std::lock_guard<std::mutex> lk(ctx->direct_mu);
+        auto it = ctx->graphs.find(gid);
+        if (it == ctx->graphs.end()) {
+            delete t;
+            return fail(GALE_ENOENT, "unknown graph");
+        }
+        Prepared *g = it->second;
+        t->batch.items = g->batch.items;
+        t->batch.out_words = g->batch.out_words;
+        t->batch.out = g->batch.out;
+        t->batch.dev_items = g->batch.dev_items;
+        t->batch.dev_hdr = g->batch.dev_hdr;
+        t->batch.host_hdr = g->batch.host_hdr;
+        t->batch.borrowed = true;
+        t->mask = g->mask;
+        t->host = false;
+        t->by_cluster = g->by_cluster;
+        hipError_t e = hipSuccess;
+        if (hipEventCreate(&t->batch.kev[0]) != hipSuccess || hipEventCreate(&t->batch.kev[1]) != hipSuccess)
+            destroy_ticket_events(t);
+        if (t->batch.kev[0]) e = hipEventRecord(t->batch.kev[0], ctx->stream);
+        if (e == hipSuccess && g->exec) e = hipGraphLaunch(g->exec, ctx->stream);
+        if (e == hipSuccess && t->batch.kev[1]) {
+            e = hipEventRecord(t->batch.kev[1], ctx->stream);
+            t->batch.kev_recorded = e == hipSuccess;
+        }
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&t->done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(t->done, ctx->stream);
+        if (e != hipSuccess) {
+            ctx->poisoned = true;
+            if (t->done) (void)hipEventDestroy(t->done);
+            destroy_ticket_events(t);
+            delete t;
+            return fail(GALE_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+        }
+        ctx->n_requests++;
+    }
+    std::lock_guard<std::mutex> g2(ctx->tick_mu);
+    const uint64_t id = ++ctx->next_ticket;
+    ctx->tickets[id] = t;
+    *ticket_out = id;
+    return GALE_OK;
+}
+
+gale_status graph_destroy(gale_ctx *ctx, uint64_t gid) {
+    std::lock_guard<std::mutex> lk(ctx->direct_mu);
+    auto it = ctx->graphs.find(gid);
+    if (it == ctx->graphs.end()) return fail(GALE_ENOENT, "unknown graph");
+    Prepared *g = it->second;
+    (void)hipStreamSynchronize(ctx->stream);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    release_batch(ctx, g->batch);
+    delete g;
+    ctx->graphs.erase(it);
+    return GALE_OK;
+}
+
 gale_status direct_poll(gale_ctx *ctx, Ticket *t, int64_t timeout_ns) {
     if (t->ready) return t->status;
     const auto t0 = std::chrono::steady_clock::now();
@@ -574,10 +785,36 @@ gale_status gale_create(const gale_config *cfg_in, gale_ctx **out) {
     e = persistent_occupancy(ctx->block_threads, true, (size_t)ctx->lds_budget, &occ);
     if (e != hipSuccess || occ <= 0) occ = 1;
     ctx->grid_lds = ctx->num_cus * occ;
+    ctx->static_lds = static_lds;
+    ctx->shared_per_block = (int64_t)prop.sharedMemPerBlock;
+    setup_classes(ctx, cfg.launch_classes);
     occ = 0;
     e = persistent_occupancy(ctx->block_threads, false, 0, &occ);
     if (e != hipSuccess || occ <= 0) occ = 1;
     ctx->grid_glob = ctx->num_cus * occ;
+    if (cfg.mode == GALE_MODE_DIRECT) {
+        // streams for the launches of one batch beyond the first (classes and
+        // the global path run side by side), default priority
+        const int naux = 3;  // up to two more classes and the global path
+        for (int i = 0; i < naux; ++i) {
+            hipStream_t s2 = nullptr;
+            hipEvent_t ev = nullptr;
+            if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+                if (s2) (void)hipStreamDestroy(s2);
+                break;
+            }
+            ctx->aux.push_back(s2);
+            ctx->join_ev.push_back(ev);
+        }
+        if (hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) != hipSuccess) ctx->fork_ev = nullptr;
+        if (!ctx->fork_ev) {
+            for (hipStream_t s2 : ctx->aux) (void)hipStreamDestroy(s2);
+            for (hipEvent_t ev : ctx->join_ev) (void)hipEventDestroy(ev);
+            ctx->aux.clear();
+            ctx->join_ev.clear();
+        }
+    }
     if (cfg.hip_stream) {
         ctx->stream = (hipStream_t)cfg.hip_stream;
         ctx->own_stream = false;
@@ -722,6 +959,73 @@ gale_status gale_release(gale_ctx *ctx, uint64_t ticket) {
 
 void *gale_stream(gale_ctx *ctx) { return ctx ? (void *)ctx->stream : nullptr; }
 
+gale_status gale_autotune(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t mask, int32_t reps,
+                          int32_t *chosen_out, double *ms_out) {
+    if (!ctx) return fail(GALE_EINVAL, "ctx is NULL");
+    if (ctx->cfg.mode != GALE_MODE_DIRECT) return fail(GALE_ESTATE, "autotune needs a DIRECT mode context");
+    if (reps < 1) return fail(GALE_EINVAL, "reps must be >= 1");
+    const int candidates[4] = {0, 2, 4, 6};
+    double ms[4] = {0, 0, 0, 0};
+    uint64_t saved_n;
+    double saved_ms;
+    {
+        std::lock_guard<std::mutex> g(ctx->direct_mu);
+        saved_n = ctx->n_timed;
+        saved_ms = ctx->kernel_ms;
+    }
+    int best = -1;
+    gale_status st = GALE_OK;
+    for (int ci = 0; ci < 4 && st == GALE_OK; ++ci) {
+        {
+            std::lock_guard<std::mutex> g(ctx->direct_mu);
+            setup_classes(ctx, candidates[ci]);
+        }
+        for (int r = 0; r <= reps && st == GALE_OK; ++r) {
+            if (r == 1) {
+                std::lock_guard<std::mutex> g(ctx->direct_mu);
+                ctx->n_timed = 0;
+                ctx->kernel_ms = 0.0;
+            }
+            uint64_t tk = 0;
+            st = gale_build(ctx, ids, n, mask, GALE_FORM_BATCHED, &tk);
+            if (st == GALE_OK) st = gale_poll(ctx, tk, -1);
+            if (tk) (void)gale_release(ctx, tk);
+        }
+        std::lock_guard<std::mutex> g(ctx->direct_mu);
+        ms[ci] = ctx->n_timed ? ctx->kernel_ms / (double)ctx->n_timed : 0.0;
+        if (st == GALE_OK && (best < 0 || ms[ci] < ms[best])) best = ci;
+    }
+    {
+        std::lock_guard<std::mutex> g(ctx->direct_mu);
+        setup_classes(ctx, best >= 0 ? candidates[best] : ctx->cfg.launch_classes);
+        ctx->n_timed = saved_n;
+        ctx->kernel_ms = saved_ms;
+    }
+    if (st != GALE_OK) return st;
+    if (chosen_out) *chosen_out = candidates[best];
+    if (ms_out)
+        for (int i = 0; i < 4; ++i) ms_out[i] = ms[i];
+    return GALE_OK;
+}
+
+gale_status gale_graph_create(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t mask, uint64_t *graph_out) {
+    if (!ctx || !graph_out) return fail(GALE_EINVAL, "NULL argument");
+    if (ctx->cfg.mode != GALE_MODE_DIRECT) return fail(GALE_ESTATE, "graphs need a DIRECT mode context");
+    return graph_create(ctx, ids, n, mask, graph_out);
+}
+
+gale_status gale_graph_launch(gale_ctx *ctx, uint64_t graph, uint64_t *ticket_out) {
+    if (!ctx || !ticket_out) return fail(GALE_EINVAL, "NULL argument");
+    if (ctx->cfg.mode != GALE_MODE_DIRECT) return fail(GALE_ESTATE, "graphs need a DIRECT mode context");
+    return graph_launch(ctx, graph, ticket_out);
+}
+
+gale_status gale_graph_destroy(gale_ctx *ctx, uint64_t graph) {
+    if (!ctx) return fail(GALE_EINVAL, "ctx is NULL");
+    if (ctx->cfg.mode != GALE_MODE_DIRECT) return fail(GALE_ESTATE, "graphs need a DIRECT mode context");
+    return graph_destroy(ctx, graph);
+}
+
 gale_status gale_get_stats(gale_ctx *ctx, gale_stats *out) {
     if (!ctx || !out) return fail(GALE_EINVAL, "NULL argument");
     std::memset(out, 0, sizeof(*out));
@@ -775,12 +1079,21 @@ void gale_destroy(gale_ctx *ctx) {
         }
         ctx->tickets.clear();
     }
+    for (auto &kv : ctx->graphs) {
+        if (kv.second->exec) (void)hipGraphExecDestroy(kv.second->exec);
+        if (kv.second->graph) (void)hipGraphDestroy(kv.second->graph);
+        delete kv.second;
+    }
+    ctx->graphs.clear();
     ctx->dev_pool.clear();
     ctx->pin_pool.clear();
     if (ctx->d_tets) (void)hipFree(ctx->d_tets);
     if (ctx->d_tid) (void)hipFree(ctx->d_tid);
     if (ctx->d_lverts) (void)hipFree(ctx->d_lverts);
     if (ctx->d_meta) (void)hipFree(ctx->d_meta);
+    for (hipStream_t s2 : ctx->aux) (void)hipStreamDestroy(s2);
+    for (hipEvent_t ev : ctx->join_ev) (void)hipEventDestroy(ev);
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }

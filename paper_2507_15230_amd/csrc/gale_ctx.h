@@ -51,8 +51,9 @@ struct Batch {
     std::vector<BlockLoc> loc;          // where each item's block lives, after finalize
     std::vector<int64_t> host_word;     // host copy offsets
     bool host_ready = false;
-    hipEvent_t kev[2] = {nullptr, nullptr};  // around the persistent LDS-path launch (DIRECT, BATCHED)
+    hipEvent_t kev[2] = {nullptr, nullptr};  // around the persistent launches (DIRECT, BATCHED)
     bool kev_recorded = false;
+    bool borrowed = false;  // buffers owned by a prepared (graph) request, not by this batch
 };
 
 struct Ticket {
@@ -63,6 +64,16 @@ struct Ticket {
     gale_status status = GALE_OK;
     hipEvent_t done = nullptr;
     std::unordered_map<int32_t, std::vector<int>> by_cluster;
+};
+
+// A batched request prepared for repeated builds: its blocks' buffer and work
+// list stay in device memory and its launches are captured in a HIP graph.
+struct Prepared {
+    Batch batch;
+    uint32_t mask = 0;
+    std::unordered_map<int32_t, std::vector<int>> by_cluster;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 // ---- serving -------------------------------------------------------------
@@ -138,6 +149,19 @@ struct gale_ctx {
     bool poisoned = false;
     int num_cus = 0, grid_lds = 1, grid_glob = 1, block_threads = 256;
     int64_t lds_budget = 0;
+    // workgroup shapes for LDS-path clusters, largest LDS first; a cluster
+    // takes the last (smallest) one its working set fits
+    struct LaunchClass {
+        int bt;          // threads per workgroup
+        int64_t budget;  // dynamic LDS bytes
+        int grid;        // persistent workgroups (CUs x occupancy)
+    };
+    std::vector<LaunchClass> classes;
+    int class_mask = 0;
+    int64_t static_lds = 0, shared_per_block = 0;
+    std::vector<hipStream_t> aux;  // DIRECT mode: streams the classes' launches run on, joined back
+    hipEvent_t fork_ev = nullptr;
+    std::vector<hipEvent_t> join_ev;
     // mesh
     bool loaded = false;
     int32_t nv = 0, ncl = 0;
@@ -153,6 +177,8 @@ struct gale_ctx {
     std::mutex direct_mu, tick_mu;
     std::unordered_map<uint64_t, gale::Ticket *> tickets;
     uint64_t next_ticket = 0;
+    std::unordered_map<uint64_t, gale::Prepared *> graphs;  // under direct_mu
+    uint64_t next_graph = 0;
     // counters
     std::atomic<uint64_t> n_requests{0}, n_blocks{0}, n_entries{0}, n_launches{0}, n_overflow{0},
         n_global_blocks{0}, n_delivered{0}, n_bytes_d2h{0}, n_tt_exhaustive{0};
@@ -166,6 +192,7 @@ gale_status fail(gale_status s, const std::string &msg);
 int32_t default_cap_tt(const ClusterMeta &m);
 int64_t lay_out_items(const gale_ctx *ctx, std::vector<WorkItem> &items, int64_t out_base_word);
 int64_t workspace_bytes(const gale_ctx *ctx, const std::vector<WorkItem> &items, int *n_global);
+void setup_classes(gale_ctx *ctx, int mask);
 gale_status upload_and_launch(gale_ctx *ctx, int form, const std::vector<WorkItem> &items, int32_t *d_out,
                               Buf *&dev_items, Buf *&dev_hdr, Buf *&host_items, Buf *&ws, hipStream_t st,
                               const hipEvent_t *kev = nullptr, bool *kev_recorded = nullptr);

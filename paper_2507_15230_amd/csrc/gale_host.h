@@ -30,6 +30,7 @@ hipError_t launch_items(const KArgs &a, bool lds_path, int block_threads, int gr
 hipError_t launch_persistent(const KArgs &a, bool lds_path, int block_threads, int grid, size_t lds,
                              hipStream_t st);
 hipError_t set_lds_limits(size_t lds);
+hipError_t launch_zero(int32_t *p, int n, hipStream_t st);  // n <= 64
 hipError_t static_lds_bytes(int64_t *bytes);  // largest static LDS of the LDS-path kernels
 hipError_t persistent_occupancy(int block_threads, bool lds_path, size_t lds, int *blocks_per_cu);
 

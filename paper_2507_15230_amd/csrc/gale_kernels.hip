@@ -921,9 +921,22 @@ __global__ __launch_bounds__(B) void gale_persistent_kernel(KArgs a) {
     }
 }
 
+// Zero n words (queue words of a captured batch: a kernel node instead of a
+// memset node, so graph replays start from zero).
+__global__ __launch_bounds__(64) void gale_zero_kernel(int32_t *p, int n) {
+    const int i = threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 // ---------------------------------------------------------------------------
 // host-side launch wrappers
 // ---------------------------------------------------------------------------
+hipError_t launch_zero(int32_t *p, int n, hipStream_t st) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(gale_zero_kernel, dim3(1), dim3(64), 0, st, p, n);
+    return hipGetLastError();
+}
+
 template <bool kL>
 static hipError_t launch_items_t(const KArgs &a, int block_threads, int grid, size_t lds, hipStream_t st) {
     (void)hipGetLastError();  // the launch status below is this launch's, not an earlier call's

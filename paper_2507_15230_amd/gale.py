@@ -26,7 +26,7 @@ class GaleConfig(C.Structure):
     _fields_ = [
         ("device", C.c_int32), ("mode", C.c_int32), ("form", C.c_int32), ("block_threads", C.c_int32),
         ("lds_bytes", C.c_int32), ("max_inflight", C.c_int32), ("cache_budget_bytes", C.c_uint64),
-        ("max_queue", C.c_int32), ("reserved", C.c_int32), ("hip_stream", C.c_void_p),
+        ("max_queue", C.c_int32), ("launch_classes", C.c_int32), ("hip_stream", C.c_void_p),
     ]
 
 
@@ -110,6 +110,10 @@ def load_library(path: str = LIB_PATH):
         "gale_strerror": ([C.c_int32], C.c_char_p),
         "gale_last_error": ([], C.c_char_p),
         "gale_destroy": ([vp], None),
+        "gale_graph_create": ([vp, i32p, C.c_int32, C.c_uint32, u64p], C.c_int32),
+        "gale_graph_launch": ([vp, C.c_uint64, u64p], C.c_int32),
+        "gale_graph_destroy": ([vp, C.c_uint64], C.c_int32),
+        "gale_autotune": ([vp, i32p, C.c_int32, C.c_uint32, C.c_int32, i32p, C.POINTER(C.c_double)], C.c_int32),
         "gale_lowerstar_classify": ([C.c_int32, i32p, i32p, i32p, i32p, i32p, i32p, C.c_int64,
                                      C.POINTER(C.c_float), C.c_int32, i32p], C.c_int32),
         "gale_consumer_run": ([vp, C.POINTER(GaleConsumerCfg), C.POINTER(GaleConsumerResult)], C.c_int32),
@@ -138,7 +142,7 @@ class Context:
 
     def __init__(self, device: int = 0, mode: str = "direct", form: str = "batched", block_threads: int = 0,
                  lds_bytes: int = 0, max_inflight: int = 0, cache_budget_bytes: int = 0, max_queue: int = 0,
-                 stream=None):
+                 stream=None, launch_classes: int = 0):
         lib = load_library()
         self._lib = lib
         cfg = GaleConfig()
@@ -150,6 +154,7 @@ class Context:
         cfg.max_inflight = max_inflight
         cfg.cache_budget_bytes = cache_budget_bytes
         cfg.max_queue = max_queue
+        cfg.launch_classes = launch_classes
         cfg.hip_stream = stream
         h = C.c_void_p()
         _check(lib.gale_create(C.byref(cfg), C.byref(h)), "gale_create")
@@ -235,6 +240,32 @@ class Context:
         s = GaleStats()
         _check(self._lib.gale_get_stats(self._h, C.byref(s)), "gale_get_stats")
         return {name: getattr(s, name) for name, _ in GaleStats._fields_ if name != "pad"}
+
+    def graph_create(self, cluster_ids, mask: int = 7) -> int:
+        a = np.ascontiguousarray(cluster_ids, np.int32)
+        g = C.c_uint64()
+        _check(self._lib.gale_graph_create(self._h, a.ctypes.data_as(C.POINTER(C.c_int32)), int(a.shape[0]),
+                                           int(mask), C.byref(g)), "gale_graph_create")
+        return g.value
+
+    def graph_launch(self, graph: int) -> int:
+        tk = C.c_uint64()
+        _check(self._lib.gale_graph_launch(self._h, int(graph), C.byref(tk)), "gale_graph_launch")
+        return tk.value
+
+    def graph_destroy(self, graph: int):
+        _check(self._lib.gale_graph_destroy(self._h, int(graph)), "gale_graph_destroy")
+
+    def autotune(self, cluster_ids, mask: int = 7, reps: int = 2):
+        """Time the launch-class candidates (0, 2, 4, 6) on this request and keep
+        the fastest; returns (chosen, {candidate: mean ms})."""
+        a = np.ascontiguousarray(cluster_ids, np.int32)
+        p = a.ctypes.data_as(C.POINTER(C.c_int32))
+        chosen = C.c_int32()
+        ms = (C.c_double * 4)()
+        _check(self._lib.gale_autotune(self._h, p, int(a.shape[0]), int(mask), int(reps), C.byref(chosen), ms),
+               "gale_autotune")
+        return chosen.value, dict(zip((0, 2, 4, 6), list(ms)))
 
     def reset_stats(self):
         _check(self._lib.gale_reset_stats(self._h), "gale_reset_stats")

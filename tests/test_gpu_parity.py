@@ -274,3 +274,75 @@ def test_refined_256_full_size_sampled():
                     bad.append((int(k), rel))
         ctx.release(tk)
     assert not bad, bad
+
+
+@pytest.mark.parametrize("classes", [7, 5])
+def test_launch_classes_equal_single_shape(classes):
+    """Clusters spread over several workgroup shapes (1024 threads with the
+    whole LDS, 512 with half, 256 with a quarter) give the same blocks as the
+    oracle, in both forms, with the global path in the same batch."""
+    gale = _gale()
+    m = meshgen.refined_mesh(36, 0.05, 3, 512, 1.0, seed=11)
+    orc = oracle.Oracle.of(m)
+    for form in ("batched", "plain"):
+        with gale.Context(form=form, launch_classes=classes) as ctx:
+            ctx.load(m.tets, m.cluster, m.nclusters)
+            compare_all(ctx, m, orc)
+            _say(form, classes, "global-path blocks", ctx.stats()["global_path_blocks"])
+
+
+def _d2h(ptr, n):
+    """n int32 from device memory (HIP runtime copy)."""
+    import ctypes as C
+    out = np.empty(n, np.int32)
+    if n:
+        hip = C.CDLL("libamdhip64.so")
+        st = hip.hipMemcpy(C.c_void_p(out.ctypes.data), C.cast(ptr, C.c_void_p), C.c_size_t(4 * n), 2)
+        assert st == 0
+    return out
+
+
+def test_graph_replays_equal_oracle():
+    """A request captured in a HIP graph (all workgroup shapes and the global
+    path) and replayed three times, with other builds in between: every block
+    of every replay equals the oracle's."""
+    gale = _gale()
+    m = meshgen.refined_mesh(36, 0.05, 3, 512, 1.0, seed=11)
+    orc = oracle.Oracle.of(m)
+    exp = {(k, rel): orc.block(k, rel) for k in range(m.nclusters) for rel in REL}
+    ids = np.arange(m.nclusters, dtype=np.int32)
+    with gale.Context(form="batched", launch_classes=6) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        g = ctx.graph_create(ids, 7)
+        for rep in range(3):
+            tk = ctx.graph_launch(g)
+            ctx.poll(tk)
+            bad = []
+            for k in range(m.nclusters):
+                for rel in REL:
+                    v = ctx.block_device(tk, k, rel)
+                    got = (_d2h(v.row_ids, v.nrows), _d2h(v.offsets, v.nrows + 1), _d2h(v.entries, v.nnz))
+                    if not all(np.array_equal(a, b) for a, b in zip(got, exp[(k, rel)])):
+                        bad.append((k, rel))
+            ctx.release(tk)
+            assert not bad, (rep, bad[:5])
+            t2 = ctx.build(ids[:7], 7, "batched")
+            ctx.poll(t2)
+            ctx.release(t2)
+            _say("graph replay", rep, "ok")
+        ctx.graph_destroy(g)
+        with pytest.raises(gale.GaleError) as ei:
+            ctx.graph_launch(g)
+        assert ei.value.status == gale.ENOENT
+
+
+def test_autotune_keeps_results():
+    gale = _gale()
+    m = meshgen.refined_mesh(36, 0.05, 3, 512, 1.0, seed=11)
+    orc = oracle.Oracle.of(m)
+    with gale.Context(form="batched") as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        chosen, ms = ctx.autotune(np.arange(m.nclusters, dtype=np.int32), 7, reps=2)
+        _say("autotune", chosen, ms)
+        assert chosen in (0, 2, 4, 6) and all(v > 0 for v in ms.values())
+        compare_all(ctx, m, orc)
