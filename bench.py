@@ -26,6 +26,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    1: "32^3 Kuhn lattice (32,768 vertices, 178,746 tetrahedra), seed-permuted, 64 Morton clusters of 512 "
+       "vertices; VT+VV+TT for every cluster in one batched launch",
+    2: "128^3 Kuhn lattice (2,097,152 vertices, 12,290,298 tetrahedra), seed-permuted, 2048 Morton clusters of "
+       "1024 vertices; VT+VV+TT for every cluster in one batched launch",
+    3: "256^3 Kuhn lattice refined by 3 rounds of centroid splits of 5% of the tetrahedra in 8 Gaussian blobs "
+       "(34,050,862 vertices, 151,309,188 tetrahedra), lognormal Morton clusters (median 512, sigma 1, 64..8192; "
+       "40,579 clusters); VT+VV+TT for every cluster in one batched launch, autotuned launch classes",
+    4: "the 256^3 refined mesh with a 16-Gaussian scalar field; batched build as for the refined mesh, then the "
+       "serving workload (40 consumer threads, 4 GB HBM relation cache)",
+}
 KERNEL_SOURCES = ["paper_2507_15230_amd/csrc/gale_kernels.hip", "paper_2507_15230_amd/csrc/gale_layout.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "persistent_kernel_traffic_128cubed.json")
 COPY_BYTES = 256 << 20
@@ -157,10 +168,19 @@ def serving_leg(mesh, args, pass_bytes: int):
     (submit -> ready) percentiles."""
     import meshgen
     from paper_2507_15230_amd import gale
-    n = int(round(mesh.nv ** (1.0 / 3.0)))
-    field = meshgen.gauss_field(mesh.coords.astype(np.float64), n, np.random.default_rng(1))
-    budget = (args.serving_budget_mb << 20) if args.serving_budget_mb else pass_bytes // 2
-    order = np.arange(mesh.nclusters, dtype=np.int32)  # cluster ids are in Morton order
+    if mesh.scalar is not None:
+        field = mesh.scalar
+    else:
+        n = int(round(mesh.nv ** (1.0 / 3.0)))
+        field = meshgen.gauss_field(mesh.coords.astype(np.float64), n, np.random.default_rng(1))
+    if args.serving_budget_mb:
+        budget = args.serving_budget_mb << 20
+    elif args.config == 4:
+        budget = 4 << 30
+    else:
+        budget = pass_bytes // 2
+    ncur = args.serving_clusters if args.serving_clusters >= 0 else (mesh.nclusters if args.config <= 2 else 4096)
+    order = np.arange(min(ncur, mesh.nclusters), dtype=np.int32)  # cluster ids are in Morton order
     log("serving leg: %d consumers, budget %.0f MB" % (args.consumers, budget / 1e6))
     ctx = gale.Context(device=0, mode="serve", cache_budget_bytes=budget, max_inflight=4,
                        block_threads=args.block_threads)
@@ -169,10 +189,11 @@ def serving_leg(mesh, args, pass_bytes: int):
     st = ctx.stats()
     ctx.close()
     out = {
-        "workload": "the benchmark mesh with a 16-Gaussian scalar field; %d native consumer threads, Morton "
+        "workload": "the benchmark mesh with its 16-Gaussian scalar field; %d native consumer threads, Morton "
                     "cursor, truncated Zipf(1.1) re-access, VT+VV+TT per access, critical points from VT and VV"
                     % args.consumers,
         "consumers": args.consumers, "cache_budget_bytes": int(budget), "max_inflight": 4,
+        "cursor_clusters": int(order.shape[0]),
         "accesses": res["accesses"], "reaccesses": res["reaccesses"], "wall_s": res["wall_s"],
         "accesses_per_s": res["accesses"] / res["wall_s"],
         "p50_us": res["lat_p50_us"], "p99_us": res["lat_p99_us"], "mean_us": res["lat_mean_us"],
@@ -208,7 +229,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="one gale_build per step instead of a graph replay")
+    ap.add_argument("--autotune", type=int, default=-1,
+                    help="pick the launch classes by timing (default: on for the refined configs 3-5)")
     ap.add_argument("--consumers", type=int, default=40)
+    ap.add_argument("--serving-clusters", type=int, default=-1,
+                    help="clusters the consumers' cursor walks (default: all on the lattices, 4096 on refined meshes)")
     ap.add_argument("--serving-budget-mb", type=int, default=0,
                     help="HBM cache budget of the serving leg; 0 = half of one full pass's block bytes")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -253,29 +279,34 @@ def main():
     ctx.load(mesh.tets, mesh.cluster, ncl)
     st0 = ctx.stats()
     mesh_bytes = st0["device_mesh_bytes"]
+    tuned = None
+    if args.autotune == 1 or (args.autotune < 0 and args.config >= 3):
+        log("autotune")
+        chosen, cand = ctx.autotune(ids, 7, reps=2)
+        tuned = {"launch_classes": chosen, "candidates_ms": {str(k): v for k, v in cand.items()}}
+    use_graph = not args.no_graph
+    graph = ctx.graph_create(ids, 7) if use_graph else None
 
-    def one_round(k):
-        tks = [ctx.build(ids, 7, "batched") for _ in range(k)]
-        for t in tks:
-            ctx.poll(t)
-        return tks
+    def step():
+        return ctx.graph_launch(graph) if use_graph else ctx.build(ids, 7, "batched")
 
-    # warmup: fills the buffer pool with as many output buffers as timed steps
+    # warmup (a graph's steps share its buffer: release each before the next)
     log("warmup")
     for _ in range(max(1, args.warmup)):
-        for t in one_round(args.steps):
-            ctx.release(t)
+        t = step()
+        ctx.poll(t)
+        ctx.release(t)
     e_before = ctx.stats()["entries_built"]
 
     # timed region: K steps back to back on the context stream.  The library
-    # records HIP events around each persistent launch on that stream; their
+    # records HIP events around each step's launches on that stream; their
     # mean is the kernel time the roofline uses.
     ctx.reset_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tks = []
     for i in range(args.steps):
-        tks.append(ctx.build(ids, 7, "batched"))
+        tks.append(step())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     for t in tks:
@@ -284,6 +315,8 @@ def main():
     entries_step = (st_t["entries_built"] - e_before) // args.steps
     for t in tks:
         ctx.release(t)
+    if graph is not None:
+        ctx.graph_destroy(graph)
     ms_kernel = st_t["kernel_ms_total"] / max(1, st_t["timed_launches"])
     ms_step = wall * 1000.0 / args.steps
     value = entries_step / (ms_step / 1000.0)
@@ -334,15 +367,14 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {
-            "workload": "128^3 Kuhn lattice (2,097,152 vertices, 12,290,298 tetrahedra), seed-permuted, "
-                        "2048 Morton clusters of 1024 vertices; VT+VV+TT for every cluster in one "
-                        "batched persistent launch" if args.config == 2 else "config %d" % args.config,
+            "workload": WORKLOADS.get(args.config, "config %d" % args.config),
             "config_index": args.config,
             "seed": 0,
             "entries_per_step": int(entries_step),
             "clusters": ncl,
-            "form": "batched",
+            "form": "batched, one hipGraph replay per step" if use_graph else "batched, one build call per step",
             "block_threads": args.block_threads,
+            "autotune": tuned,
             "load_seconds": st0["load_seconds"],
             "global_path_blocks_per_step": int(st["global_path_blocks"] // max(1, st["requests"])),
         },
