@@ -36,7 +36,7 @@ import numpy as np
 __all__ = [
     "Mesh", "kuhn_grid", "morton_keys", "clusters_fixed", "clusters_lognormal",
     "refine", "grid_mesh", "refined_mesh", "config", "CONFIGS",
-    "cube", "fig1_toy", "fig4_example", "single_tet", "random_small",
+    "cube", "fig1_toy", "fig4_example", "single_tet", "random_small", "fans", "gauss_field",
 ]
 
 
@@ -387,6 +387,30 @@ def fig4_example() -> Mesh:
 def single_tet() -> Mesh:
     return Mesh(tets=np.array([[0, 1, 2, 3]], dtype=np.int32),
                 cluster=np.zeros(4, dtype=np.int32), nclusters=1, meta={"kind": "single"})
+
+
+def fans(ks=(16, 32, 33, 64, 65, 128, 129, 200, 300, 520), nclusters: int = 6, seed: int = 0) -> Mesh:
+    """High-valence vertices: one closed fan per k, each a centre vertex, a
+    top and a bottom vertex and a ring of k vertices, with tetrahedra
+    (centre, top, r_i, r_i+1) and (centre, bottom, r_i, r_i+1) around the
+    ring.  The centre lies in 2k tetrahedra, top and bottom in k, ring
+    vertices in 4; every triangle is shared by at most two tetrahedra.
+    Random cluster labels, then random vertex and tetrahedron ids.  Draw
+    order: cluster labels, vperm, tperm."""
+    rng = np.random.default_rng(seed)
+    tets, base = [], 0
+    for k in ks:
+        c, top, bot = base, base + 1, base + 2
+        ring = base + 3 + np.arange(k)
+        nxt = np.roll(ring, -1)
+        for apex in (top, bot):
+            tets.append(np.stack([np.full(k, c), np.full(k, apex), ring, nxt], axis=1))
+        base += k + 3
+    tets = np.concatenate(tets).astype(np.int32)
+    cluster = rng.integers(0, nclusters, size=base).astype(np.int32)
+    tets, cluster, _, _ = _permute(rng, tets, cluster, None, None)
+    return Mesh(tets=np.ascontiguousarray(tets), cluster=cluster, nclusters=nclusters,
+                meta={"kind": "fans", "ks": list(ks), "seed": seed})
 
 
 def random_small(seed: int, n: int = 4, nclusters: int = 5, drop: float = 0.3,

@@ -185,8 +185,93 @@ __device__ __forceinline__ void sort32(uint32_t (&v)[32]) {
     }
 }
 
-// ---------------------------------------------------------------------------
-// one cluster
+// One wave sorts a list of n keys (n wave-uniform, every lane active) and
+// writes it ascending to dst[0, n); key(i) gives the i-th key (< 2^31, all
+// distinct).  Up to 64 K keys: a bitonic network over elements e = lane + 64 k
+// (partners across lanes by shuffles for strides below 64, within a lane's
+// registers above).
+template <int K, class F>
+__device__ __forceinline__ void wave_bitonic(int n, const F &key, int32_t *dst) {
+    const int lane = threadIdx.x & 63;
+    uint32_t v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = lane + 64 * k;
+        v[k] = e < n ? (uint32_t)key(e) : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int s = 2; s <= 64 * K; s <<= 1) {
+#pragma unroll
+        for (int j = s >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {
+                // s >= 128: bit s of e = lane + 64 k is bit s of 64 k
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int l = k ^ (j >> 6);
+                    if (l > k) {
+                        if (((64 * k) & s) == 0)
+                            cswap_u(v[k], v[l]);
+                        else
+                            cswap_u(v[l], v[k]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int e = lane + 64 * k;
+                    const uint32_t w = (uint32_t)__shfl_xor((int)v[k], j, 64);
+                    // the lower element of an ascending pair keeps the minimum
+                    const bool keep_min = ((e & j) == 0) == ((e & s) == 0);
+                    v[k] = keep_min ? min(v[k], w) : max(v[k], w);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = lane + 64 * k;
+        if (e < n) dst[e] = (int32_t)v[k];
+    }
+}
+
+// Longer lists: each key goes to its rank (the number of smaller keys),
+// 256 keys per sweep over the list.
+template <class F>
+__device__ __forceinline__ void wave_rank_sort(int n, const F &key, int32_t *dst) {
+    constexpr int K = 4;
+    const int lane = threadIdx.x & 63;
+    for (int i0 = 0; i0 < n; i0 += 64 * K) {
+        uint32_t x[K];
+        int rk[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = i0 + lane + 64 * k;
+            x[k] = i < n ? (uint32_t)key(i) : 0xFFFFFFFFu;
+            rk[k] = 0;
+        }
+        for (int j = 0; j < n; ++j) {
+            const uint32_t y = (uint32_t)key(j);
+#pragma unroll
+            for (int k = 0; k < K; ++k) rk[k] += y < x[k];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (i0 + lane + 64 * k < n) dst[rk[k]] = (int32_t)x[k];
+    }
+}
+
+template <class F>
+__device__ __forceinline__ void wave_sort(int n, const F &key, int32_t *dst) {
+    if (n <= 64)
+        wave_bitonic<1>(n, key, dst);
+    else if (n <= 128)
+        wave_bitonic<2>(n, key, dst);
+    else if (n <= 256)
+        wave_bitonic<4>(n, key, dst);
+    else
+        wave_rank_sort(n, key, dst);
+}
+
 // ---------------------------------------------------------------------------
 // one cluster
 // ---------------------------------------------------------------------------
@@ -274,7 +359,7 @@ __device__ __forceinline__ int face_index(int4 s, int a, int b, int c) {
 //   VV  the union of the vertices of a row's tetrahedra, through a bitmap over
 //       the local table, which is in original id order.
 template <int B, bool kL>
-__device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterMeta &m, const Plan &pl,
+__device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, const WorkItem &it, const ClusterMeta &m, const Plan &pl,
                               char *smem, char *ws) {
     using PosT = typename std::conditional<kL, uint16_t, int32_t>::type;
     using LidT = typename std::conditional<kL, uint16_t, int32_t>::type;
@@ -788,34 +873,44 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
         if ((mask & kRelVT) && vt_ok) {
             int32_t *buf = reinterpret_cast<int32_t *>(smem + pl.lt);
             const int bcap = kL ? (int)((pl.rix - pl.lt) / 4) : 0;
-            // sort row r's ids into dst (n <= 32 in registers, longer in place)
-            auto sort_row = [&](int r, int32_t *dst) {
+            // rows of at most 32 entries: one thread each, in registers;
+            // longer rows: the wave of the row's thread, after its short rows
+            auto sort_short = [&](int r, int32_t *dst) {
                 const int s0 = cnt[r], n = cnt[r + 1] - s0;
-                if (n <= 32) {
-                    uint32_t v[32];
+                uint32_t v[32];
 #pragma unroll
-                    for (int i = 0; i < 32; ++i)
-                        v[i] = i < n ? (uint32_t)(idg[lvt[s0 + i]] & kIdMask) : 0xFFFFFFFFu;
-                    sort32(v);
+                for (int i = 0; i < 32; ++i)
+                    v[i] = i < n ? (uint32_t)(idg[lvt[s0 + i]] & kIdMask) : 0xFFFFFFFFu;
+                sort32(v);
 #pragma unroll
-                    for (int i = 0; i < 32; ++i)
-                        if (i < n) dst[i] = (int32_t)v[i];
-                } else {
-                    for (int i = 0; i < n; ++i) {
-                        const int32_t x = idg[lvt[s0 + i]] & kIdMask;
-                        int j = i - 1;
-                        while (j >= 0 && dst[j] > x) {
-                            dst[j + 1] = dst[j];
-                            --j;
-                        }
-                        dst[j + 1] = x;
-                    }
+                for (int i = 0; i < 32; ++i)
+                    if (i < n) dst[i] = (int32_t)v[i];
+            };
+            // rows [rb, rb + B) with row rb + tid for this thread; dst_of(r)
+            // is where row r's sorted list goes
+            auto sort_rows = [&](int rb, int re, auto dst_of) {
+                const int r = rb + tid;
+                bool lng = false;
+                if (r < re) {
+                    if (cnt[r + 1] - cnt[r] <= 32)
+                        sort_short(r, dst_of(r));
+                    else
+                        lng = true;
+                }
+                unsigned long long bal = __ballot(lng);
+                while (bal) {
+                    const int rr = rb + (tid & ~63) + __ffsll((long long)bal) - 1;
+                    bal &= bal - 1;
+                    const int s0 = cnt[rr];
+                    wave_sort(
+                        cnt[rr + 1] - s0, [&](int i) { return idg[lvt[s0 + i]] & kIdMask; }, dst_of(rr));
                 }
             };
             for (int r = tid; r < nV; r += B) blk[lay.vt_off + r] = cnt[r];
             if (tid == 0) blk[lay.vt_off + nV] = cnt[nV];
             if constexpr (!kL) {
-                for (int r = tid; r < nV; r += B) sort_row(r, blk + lay.vt_ent + cnt[r]);
+                for (int rb = 0; rb < nV; rb += B)
+                    sort_rows(rb, nV, [&](int r) { return blk + lay.vt_ent + cnt[r]; });
                 __syncthreads();
             } else {
                 int r0 = 0;
@@ -827,17 +922,16 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
                         if (cnt[mid] - cnt[r0] <= bcap) lo = mid;
                         else hi = mid - 1;
                     }
-                    const int r1 = lo;
-                    if (r1 == r0) {
-                        // row r0 alone exceeds the buffer: sorted in place in the block
-                        if (tid == 0) sort_row(r0, blk + lay.vt_ent + cnt[r0]);
+                    const int e0 = cnt[r0];
+                    if (lo == r0) {
+                        // row r0 alone exceeds the buffer: sorted straight into the block
+                        sort_rows(r0, r0 + 1, [&](int r) { return blk + lay.vt_ent + cnt[r]; });
                         __syncthreads();
                         r0 += 1;
                         continue;
                     }
-                    const int e0 = cnt[r0];
-                    const int r = r0 + tid;
-                    if (r < r1) sort_row(r, buf + (cnt[r] - e0));
+                    const int r1 = lo;
+                    sort_rows(r0, r1, [&](int r) { return buf + (cnt[r] - e0); });
                     __syncthreads();
                     const int ne = cnt[r1] - e0;
                     for (int e = tid; e < ne; e += B) blk[lay.vt_ent + e0 + e] = buf[e];
@@ -872,7 +966,7 @@ __device__ void build_cluster(const KArgs &a, const WorkItem &it, const ClusterM
 // sorts items by path with the same plan functions; an item that does not
 // fit what it was sent to is reported in its header and skipped.
 template <int B, bool kL>
-__device__ void process_item(const KArgs &a, const WorkItem &it, char *smem, char *ws) {
+__device__ __attribute__((always_inline)) void process_item(const KArgs &a, const WorkItem &it, char *smem, char *ws) {
     const ClusterMeta m = a.s.meta[it.cluster];
     const Plan lp = lds_plan(m, it.mask, a.lds_budget, B);
     const bool ok = kL ? (lp.ok != 0) : (ws != nullptr);

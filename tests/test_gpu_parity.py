@@ -346,3 +346,23 @@ def test_autotune_keeps_results():
         _say("autotune", chosen, ms)
         assert chosen in (0, 2, 4, 6) and all(v > 0 for v in ms.values())
         compare_all(ctx, m, orc)
+
+
+@pytest.mark.parametrize("path", ["lds", "global", "one_cluster", "plain"])
+def test_high_valence_rows(path):
+    """VT rows of 32, 33, 64, 65, 128, 129, 256, 258, 400, 600 and 1040
+    entries (the lengths where a row's sort changes method) on the LDS path,
+    the global-workspace path, a whole-mesh cluster and the plain form."""
+    gale = _gale()
+    m = meshgen.fans(seed=11)
+    if path == "one_cluster":
+        m = meshgen.Mesh(tets=m.tets, cluster=np.zeros(m.nv, np.int32), nclusters=1)
+    _say("fans", path, m.nt)
+    orc = oracle.Oracle.of(m)
+    kw = {"lds_bytes": 256} if path == "global" else {}
+    with gale.Context(form="plain" if path == "plain" else "batched", **kw) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        compare_all(ctx, m, orc)
+        compare_all(ctx, m, orc, mask=1)
+        if path == "global":
+            assert ctx.stats()["global_path_blocks"] > 0

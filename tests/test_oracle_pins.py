@@ -327,3 +327,28 @@ def test_pins_pass_on_oracle():
 def test_planted_mistakes(m):
     res = _all_pins(m)
     assert not all(res.values()), "planted mistake %d (%s) passed every pin" % (m, MUTATIONS[m])
+
+
+def test_fan_closed_forms():
+    """Closed fans: the centre of a ring of k lies in 2k tetrahedra and has
+    k + 2 neighbours, top and bottom lie in k and have k + 1, a ring vertex lies
+    in 4 and has 5; every tetrahedron has exactly 3 face neighbours (its
+    fourth face, opposite the centre, is on the boundary)."""
+    ks = (3, 16, 33, 70)
+    m = meshgen.fans(ks, nclusters=4, seed=5)
+    orc = oracle.Oracle.of(m)
+    blocks = pinlib.gather_all(orc.block, m.nclusters)
+    vt = dict(zip(*blocks[REL_VT]))
+    vv = dict(zip(*blocks[REL_VV]))
+    tt = dict(zip(*blocks[REL_TT]))
+    assert sorted(tt) == list(range(m.nt)) and all(len(l) == 3 for l in tt.values())
+    # the valence multiset over all vertices, fan by fan
+    exp_vt, exp_vv = [], []
+    for k in ks:
+        exp_vt += [2 * k, k, k] + [4] * k
+        exp_vv += [k + 2, k + 1, k + 1] + [5] * k
+    assert sorted(len(l) for l in vt.values()) == sorted(exp_vt)
+    assert sorted(len(l) for l in vv.values()) == sorted(exp_vv)
+    # each VT list is the set of tetrahedra containing the vertex, ascending
+    for v, l in vt.items():
+        assert l == sorted(np.nonzero((m.tets == v).any(1))[0].tolist())
