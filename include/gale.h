@@ -77,7 +77,9 @@ typedef struct {
     int32_t  launch_classes;      /* BATCHED form: which workgroup shapes clusters may use, bit 0 = 1024 threads with
                                      the whole LDS, bit 1 = 512 threads with half, bit 2 = 256 threads with a
                                      quarter (several workgroups per CU); each cluster takes the smallest shape its
-                                     working set fits.  0 = the 1024-thread shape only. */
+                                     working set fits.  0 = the 1024-thread shape only.  Bit 3 (all forms): the
+                                     global-memory path keeps every working array in global memory instead of
+                                     placing its most used ones in LDS when they fit (used by tests). */
     void    *hip_stream;          /* borrowed hipStream_t for DIRECT mode work, or NULL for a library-owned stream.
                                      Must outlive the context. */
 } gale_config;
@@ -133,6 +135,7 @@ typedef struct {
        stream */
     uint64_t timed_launches;
     double   kernel_ms_total;
+    uint64_t hybrid_path_blocks;    /* of global_path_blocks, those run with their most used arrays in LDS */
 } gale_stats;
 
 /* Create a context on cfg->device.  cfg may be NULL for defaults. */

@@ -189,11 +189,11 @@ gale_status launch_batch(gale_ctx *ctx, int form, int32_t *d_out, int32_t *d_hdr
                 ctx->n_launches++;
             }
         }
-        a.lds_budget = (int32_t)ctx->lds_budget;
+        a.lds_budget = (int32_t)ctx->glob_lds;
         for (int j = 0; j < n_glob && e == hipSuccess; ++j, ++i) {
             a.items = d_items + i;
             a.nitems = 1;
-            e = launch_items(a, false, ctx->block_threads, 1, 0, st);
+            e = launch_items(a, false, ctx->block_threads, 1, (size_t)ctx->glob_lds, st);
             ctx->n_launches++;
         }
     } else {
@@ -227,8 +227,9 @@ gale_status launch_batch(gale_ctx *ctx, int form, int32_t *d_out, int32_t *d_hdr
                 a.lds_budget = (int32_t)lc.budget;
                 e = launch_persistent(a, true, lc.bt, std::min<int>(l.n, lc.grid), (size_t)lc.budget, s2);
             } else {
-                a.lds_budget = (int32_t)ctx->lds_budget;
-                e = launch_persistent(a, false, ctx->block_threads, std::min<int>(l.n, ctx->grid_glob), 0, s2);
+                a.lds_budget = (int32_t)ctx->glob_lds;
+                e = launch_persistent(a, false, ctx->block_threads, std::min<int>(l.n, ctx->grid_glob),
+                                      (size_t)ctx->glob_lds, s2);
             }
             ctx->n_launches++;
             if (e == hipSuccess && use_aux && li > 0) {
@@ -269,6 +270,8 @@ gale_status stage_items(gale_ctx *ctx, int form, const std::vector<WorkItem> &it
     order.insert(order.end(), glob.begin(), glob.end());
     wsb = workspace_bytes(ctx, glob, nullptr);
     ctx->n_global_blocks += n_glob;
+    for (const WorkItem &it : glob)
+        if (hyb_plan(ctx->meta[it.cluster], it.mask, ctx->glob_lds, ctx->block_threads).ok) ctx->n_hybrid_blocks++;
     const int slots = form == GALE_FORM_PLAIN ? 1 : std::min<int>(std::max(n_glob, 1), ctx->grid_glob);
     dev_items = ctx->dev_pool.acquire((size_t)n * sizeof(WorkItem) + 64, &e);
     dev_hdr = ctx->dev_pool.acquire((size_t)n * 32 + 64, &e);
@@ -788,10 +791,19 @@ gale_status gale_create(const gale_config *cfg_in, gale_ctx **out) {
     ctx->static_lds = static_lds;
     ctx->shared_per_block = (int64_t)prop.sharedMemPerBlock;
     setup_classes(ctx, cfg.launch_classes);
+    // global path: as many workgroups per CU as without LDS, each with its
+    // share of the LDS for the hybrid form
     occ = 0;
     e = persistent_occupancy(ctx->block_threads, false, 0, &occ);
     if (e != hipSuccess || occ <= 0) occ = 1;
-    ctx->grid_glob = ctx->num_cus * occ;
+    if (!(cfg.launch_classes & 8)) {
+        int64_t g = ctx->shared_per_block / occ - static_lds;
+        g = std::min<int64_t>(g, ctx->lds_budget) / 16 * 16;
+        ctx->glob_lds = std::max<int64_t>(g, 0);
+    }
+    int occ2 = 0;
+    e = persistent_occupancy(ctx->block_threads, false, (size_t)ctx->glob_lds, &occ2);
+    ctx->grid_glob = ctx->num_cus * ((e != hipSuccess || occ2 <= 0) ? 1 : occ2);
     if (cfg.mode == GALE_MODE_DIRECT) {
         // streams for the launches of one batch beyond the first (classes and
         // the global path run side by side), default priority
@@ -1041,6 +1053,7 @@ gale_status gale_get_stats(gale_ctx *ctx, gale_stats *out) {
     out->kernel_launches = ctx->n_launches;
     out->overflow_reruns = ctx->n_overflow;
     out->global_path_blocks = ctx->n_global_blocks;
+    out->hybrid_path_blocks = ctx->n_hybrid_blocks;
     out->tt_exhaustive_blocks = ctx->n_tt_exhaustive;
     out->entries_delivered = ctx->n_delivered;
     out->bytes_d2h = ctx->n_bytes_d2h;

@@ -149,6 +149,9 @@ struct gale_ctx {
     bool poisoned = false;
     int num_cus = 0, grid_lds = 1, grid_glob = 1, block_threads = 256;
     int64_t lds_budget = 0;
+    // dynamic LDS of a global-path workgroup (the hybrid form's arrays), 0
+    // when the global path keeps every array in global memory
+    int64_t glob_lds = 0;
     // workgroup shapes for LDS-path clusters, largest LDS first; a cluster
     // takes the last (smallest) one its working set fits
     struct LaunchClass {
@@ -181,7 +184,7 @@ struct gale_ctx {
     uint64_t next_graph = 0;
     // counters
     std::atomic<uint64_t> n_requests{0}, n_blocks{0}, n_entries{0}, n_launches{0}, n_overflow{0},
-        n_global_blocks{0}, n_delivered{0}, n_bytes_d2h{0}, n_tt_exhaustive{0};
+        n_global_blocks{0}, n_hybrid_blocks{0}, n_delivered{0}, n_bytes_d2h{0}, n_tt_exhaustive{0};
     uint64_t n_timed = 0;     // timed persistent launches (under direct_mu)
     double kernel_ms = 0.0;   // their total duration
     gale::Serve serve;

@@ -48,7 +48,7 @@ constexpr int32_t kIdMask = 0x7fffffff;   // tetrahedron id (bit 31: internal)
 constexpr int32_t kVidMask = 0x3fffffff;  // vertex id (bit 31: row, bit 30: lower cluster)
 
 #ifdef GALE_PHASE_TIMING
-__device__ unsigned long long g_phase_cycles[32];
+__device__ unsigned long long g_phase_cycles[48];
 // wave-level event counters (phase-timing builds only): slot k += 1 once per
 // wave that reaches the mark with at least one active lane
 #define WAVE_COUNT(k)                                                                      \
@@ -62,7 +62,8 @@ __device__ unsigned long long g_phase_cycles[32];
         __syncthreads();                                                           \
         if (threadIdx.x == 0) {                                                    \
             const unsigned long long now = __builtin_amdgcn_s_memtime();          \
-            atomicAdd(&g_phase_cycles[(k)], now - phase_t0);                       \
+            atomicAdd(&g_phase_cycles[(k) + (kL ? 0 : kH ? 32 : 16)], now - phase_t0); \
+            if ((k) == 0) atomicAdd(&g_phase_cycles[(kL ? 0 : kH ? 32 : 16) + 15], 1ull); \
             phase_t0 = now;                                                        \
         }                                                                          \
     } while (0)
@@ -358,7 +359,7 @@ __device__ __forceinline__ int face_index(int4 s, int a, int b, int c) {
 //   VT  a row's list, ordered by original tetrahedron id;
 //   VV  the union of the vertices of a row's tetrahedra, through a bitmap over
 //       the local table, which is in original id order.
-template <int B, bool kL>
+template <int B, bool kL, bool kH>
 __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, const WorkItem &it, const ClusterMeta &m, const Plan &pl,
                               char *smem, char *ws) {
     using PosT = typename std::conditional<kL, uint16_t, int32_t>::type;
@@ -378,6 +379,8 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
     int32_t *blk = a.out + it.out_word;
     const BlockLayout lay = block_layout(mask, nV, nT, m.nnzVT, it.cap_vv, it.cap_tt);
     char *base = kL ? smem : ws;
+    // the most used arrays: in LDS on the LDS path and on the hybrid global path
+    char *hot = (kL || kH) ? smem : ws;
     ushort4 *lt = reinterpret_cast<ushort4 *>(smem + pl.lt);
 
     if (tid == 0) {
@@ -442,7 +445,7 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
         using CL = Cells<kL>;
         using CT = typename CL::T;
         CT *win = reinterpret_cast<CT *>(base + pl.win);
-        CT *ht = reinterpret_cast<CT *>(base + pl.ht);
+        CT *ht = reinterpret_cast<CT *>(hot + pl.ht);
         uint32_t *win32 = reinterpret_cast<uint32_t *>(win);
         uint32_t *ht32 = reinterpret_cast<uint32_t *>(ht);
         const int H = pl.H;
@@ -454,7 +457,7 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
         using Look = std::integral_constant<bool, false>;
 
         // lower-cluster vertices: a face holding one is no face of a TT row
-        uint32_t *lowb = reinterpret_cast<uint32_t *>(base + pl.lowb);
+        uint32_t *lowb = reinterpret_cast<uint32_t *>(hot + pl.lowb);
         {
             const int lane = tid & 63, nwords = (L + 31) >> 5;
             for (int w0 = (tid >> 6) * 2; w0 < nwords; w0 += (B / 64) * 2) {
@@ -564,9 +567,9 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
         }
         __syncthreads();
         PHASE_MARK(1);
-        // tetrahedron ids: from a copy over the face table when it fits (LDS path)
+        // tetrahedron ids: from a copy over the face table when it fits (LDS)
         int32_t *idl = reinterpret_cast<int32_t *>(ht);
-        const bool ids_lds = kL && 2 * (int64_t)H >= 4 * (int64_t)ntot;
+        const bool ids_lds = (kL || kH) && (int64_t)sizeof(CT) * H >= 4 * (int64_t)ntot;
         if (ids_lds) {
             for (int i = tid; i < ntot; i += B) idl[i] = idg[i];
             __syncthreads();
@@ -665,11 +668,11 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
     }
 
     if (want_v) {
-        LidT *rix = reinterpret_cast<LidT *>(base + pl.rix);
-        LidT *rowl = reinterpret_cast<LidT *>(base + pl.rowl);
-        int32_t *cnt = reinterpret_cast<int32_t *>(base + pl.cnt);
+        LidT *rix = reinterpret_cast<LidT *>(hot + pl.rix);
+        LidT *rowl = reinterpret_cast<LidT *>(hot + pl.rowl);
+        int32_t *cnt = reinterpret_cast<int32_t *>(hot + pl.cnt);
         PosT *lvt = reinterpret_cast<PosT *>(base + pl.lvt);
-        uint32_t *wbm = reinterpret_cast<uint32_t *>(base + pl.wbm);
+        uint32_t *wbm = reinterpret_cast<uint32_t *>(hot + pl.wbm);
         constexpr LidT kNoRow = (LidT)-1;
 
         // rows: row index of each local vertex, local id of each row, row ids
@@ -980,10 +983,15 @@ __device__ __attribute__((always_inline)) void process_item(const KArgs &a, cons
         return;
     }
     if constexpr (kL) {
-        build_cluster<B, true>(a, it, m, lp, smem, ws);
+        build_cluster<B, true, false>(a, it, m, lp, smem, ws);
     } else {
-        const Plan gp = ws_plan(m, it.mask, B);
-        build_cluster<B, false>(a, it, m, gp, smem, ws);
+        const Plan hp = hyb_plan(m, it.mask, a.lds_budget, B);
+        if (hp.ok) {
+            build_cluster<B, false, true>(a, it, m, hp, smem, ws);
+        } else {
+            const Plan gp = ws_plan(m, it.mask, B);
+            build_cluster<B, false, false>(a, it, m, gp, smem, ws);
+        }
     }
 }
 
@@ -1059,19 +1067,23 @@ static hipError_t launch_persistent_t(const KArgs &a, int block_threads, int gri
 
 hipError_t launch_items(const KArgs &a, bool lds_path, int block_threads, int grid, size_t lds, hipStream_t st) {
     return lds_path ? launch_items_t<true>(a, block_threads, grid, lds, st)
-                    : launch_items_t<false>(a, block_threads, grid, 0, st);
+                    : launch_items_t<false>(a, block_threads, grid, lds, st);
 }
 
 hipError_t launch_persistent(const KArgs &a, bool lds_path, int block_threads, int grid, size_t lds,
                              hipStream_t st) {
     return lds_path ? launch_persistent_t<true>(a, block_threads, grid, lds, st)
-                    : launch_persistent_t<false>(a, block_threads, grid, 0, st);
+                    : launch_persistent_t<false>(a, block_threads, grid, lds, st);
 }
 
+// every builder kernel takes dynamic LDS (the global path for its hybrid form)
 static const void *const kLdsKernels[] = {
-    (const void *)gale_items_kernel<256, true>,      (const void *)gale_items_kernel<512, true>,
-    (const void *)gale_items_kernel<1024, true>,     (const void *)gale_persistent_kernel<256, true>,
-    (const void *)gale_persistent_kernel<512, true>, (const void *)gale_persistent_kernel<1024, true>,
+    (const void *)gale_items_kernel<256, true>,       (const void *)gale_items_kernel<512, true>,
+    (const void *)gale_items_kernel<1024, true>,      (const void *)gale_persistent_kernel<256, true>,
+    (const void *)gale_persistent_kernel<512, true>,  (const void *)gale_persistent_kernel<1024, true>,
+    (const void *)gale_items_kernel<256, false>,      (const void *)gale_items_kernel<512, false>,
+    (const void *)gale_items_kernel<1024, false>,     (const void *)gale_persistent_kernel<256, false>,
+    (const void *)gale_persistent_kernel<512, false>, (const void *)gale_persistent_kernel<1024, false>,
 };
 
 hipError_t static_lds_bytes(int64_t *bytes) {
@@ -1098,7 +1110,7 @@ hipError_t set_lds_limits(size_t lds) {
 extern "C" int gale_debug_phase_cycles(unsigned long long *out, int reset) {
     hipError_t e = hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase_cycles), sizeof(g_phase_cycles));
     if (reset) {
-        unsigned long long z[32] = {0};
+        unsigned long long z[48] = {0};
         hipMemcpyToSymbol(HIP_SYMBOL(g_phase_cycles), z, sizeof(z));
     }
     return (int)e;
@@ -1114,10 +1126,10 @@ hipError_t persistent_occupancy(int block_threads, bool lds_path, size_t lds, in
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<256, true>, 256, lds);
     }
     if (block_threads == 1024)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<1024, false>, 1024, 0);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<1024, false>, 1024, lds);
     if (block_threads == 512)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<512, false>, 512, 0);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<256, false>, 256, 0);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<512, false>, 512, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, gale_persistent_kernel<256, false>, 256, lds);
 }
 
 }  // namespace gale

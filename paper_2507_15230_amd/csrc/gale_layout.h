@@ -236,6 +236,48 @@ GALE_HD Plan lds_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32
     return p;
 }
 
+// Global path with its most used arrays in LDS (a workgroup of this path
+// fills its compute unit's registers, so its LDS is otherwise idle): the face
+// table (32-bit cells) and the lower-cluster bits while TT runs; the row
+// index, row local ids, VT counts and VV bitmaps while VT / VV run.  The
+// partner cells and the local VT lists stay in the workspace slice (win and
+// lvt are offsets there, both from its start since TT is finished first),
+// and the stream is read from global memory.  bytes is the LDS used.
+GALE_HD Plan hyb_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32_t block_threads) {
+    Plan p{};
+    const bool tt = (mask & kRelTT) != 0;
+    const bool v = (mask & (kRelVT | kRelVV)) != 0;
+    const bool vv = (mask & kRelVV) != 0;
+    p.win = 0;
+    p.lvt = 0;
+    p.lowb = 0;
+    p.ht = tt ? align16((int64_t)((m.L + 31) / 32) * 4) : 0;
+    int64_t h = tt ? (budget - p.ht) / 4 : 0;
+    const int64_t hmax = face_cells_max(m.nT);
+    h = h > hmax ? hmax : h;
+    h = h < 0 ? 0 : h;
+    p.H = (int32_t)h;
+    p.P = tt ? face_passes(m.nT, h) : 0;
+    const int64_t tt_end = p.ht + 4 * h;
+    p.W = (m.L + 31) / 32;
+    p.rix = 0;
+    p.rowl = p.rix + (v ? align16((int64_t)m.L * 4) : 0);
+    p.cnt = p.rowl + (v ? align16((int64_t)m.nV * 4) : 0);
+    p.wbm = p.cnt + (v ? align16(((int64_t)m.nV + 1) * 4) : 0);
+    p.G = 16;
+    int64_t v_end = p.wbm + (vv ? align16((int64_t)(block_threads / 16) * p.W * 4) : 0);
+    if (v_end > budget) {
+        p.G = 32;
+        v_end = p.wbm + (vv ? align16((int64_t)(block_threads / 32) * p.W * 4) : 0);
+    }
+    p.lvl = v_end;
+    p.bytes = tt_end > v_end ? tt_end : v_end;
+    const bool tt_ok = !tt || (h >= 64 && p.P <= kMaxFacePasses / 2);
+    const bool v_ok = !v || v_end <= budget;
+    p.ok = (tt_ok && v_ok) ? 1 : 0;
+    return p;
+}
+
 // Global path: the same arrays in the workgroup's workspace slice with 32-bit
 // ids, positions and cells; the stream is read from global memory.  TT and
 // VT / VV both start at the slice base (TT is finished first).

@@ -53,7 +53,7 @@ class GaleStats(C.Structure):
         ("lat_p50_us", C.c_double), ("lat_p99_us", C.c_double), ("lat_mean_us", C.c_double),
         ("lat_max_us", C.c_double), ("lat_count", C.c_uint64),
         ("stage_queue_us", C.c_double), ("stage_build_us", C.c_double), ("stage_copy_us", C.c_double),
-        ("timed_launches", C.c_uint64), ("kernel_ms_total", C.c_double),
+        ("timed_launches", C.c_uint64), ("kernel_ms_total", C.c_double), ("hybrid_path_blocks", C.c_uint64),
     ]
 
 

@@ -221,23 +221,58 @@ def test_error_paths():
         assert ei.value.status == gale.ESTATE
 
 
-def test_refined_lognormal_clusters():
+_REFINED36 = []
+
+
+def _refined36():
+    if not _REFINED36:
+        m = meshgen.refined_mesh(36, 0.05, 3, 512, 1.0, seed=11)
+        _REFINED36.append((m, oracle.Oracle.of(m)))
+    return _REFINED36[0]
+
+
+@pytest.mark.parametrize("classes", [0, 8])
+def test_refined_lognormal_clusters(classes):
     """Blob-refined lattice (three rounds of centroid splits on 5% of the
     tetrahedra) with lognormal cluster capacities up to 8192: high vertex
-    valences and clusters too large for LDS (global path)."""
+    valences and clusters too large for LDS (global path; its hybrid form,
+    most used arrays in LDS, unless bit 3 of launch_classes keeps them all in
+    global memory)."""
     gale = _gale()
-    m = meshgen.refined_mesh(36, 0.05, 3, 512, 1.0, seed=11)
-    _say("refined", m.nv, m.nt, m.nclusters)
-    orc = oracle.Oracle.of(m)
+    m, orc = _refined36()
+    _say("refined", m.nv, m.nt, m.nclusters, "classes", classes)
     for form in ("batched", "plain"):
-        with gale.Context(form=form) as ctx:
+        with gale.Context(form=form, launch_classes=classes) as ctx:
             ctx.load(m.tets, m.cluster, m.nclusters)
             compare_all(ctx, m, orc)
             st = ctx.stats()
-            _say(form, "global-path blocks", st["global_path_blocks"], "exhaustive TT", st["tt_exhaustive_blocks"])
+            _say(form, "global-path blocks", st["global_path_blocks"], "hybrid", st["hybrid_path_blocks"],
+                 "exhaustive TT", st["tt_exhaustive_blocks"])
             # every face is shared by at most two tetrahedra here: the face
             # table pairs all of them (no fallback to exhaustive pairing)
             assert st["tt_exhaustive_blocks"] == 0
+            assert st["global_path_blocks"] > 0
+            if classes & 8:
+                assert st["hybrid_path_blocks"] == 0
+            else:
+                assert st["hybrid_path_blocks"] > 0
+
+
+@pytest.mark.parametrize("lds", [12288, 32768, 65536])
+def test_hybrid_path_small_budgets(lds):
+    """Smaller LDS budgets send more clusters to the global path and make its
+    hybrid form split the face table into several passes."""
+    gale = _gale()
+    m, orc = _refined36()
+    _say("refined hybrid budget", lds)
+    with gale.Context(form="batched", lds_bytes=lds) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        compare_all(ctx, m, orc)
+        compare_all(ctx, m, orc, mask=4)
+        compare_all(ctx, m, orc, mask=3)
+        st = ctx.stats()
+        _say("global", st["global_path_blocks"], "hybrid", st["hybrid_path_blocks"])
+        assert st["hybrid_path_blocks"] > 0
 
 
 def test_refined_256_full_size_sampled():
