@@ -258,14 +258,27 @@ gale_status stage_items(gale_ctx *ctx, int form, const std::vector<WorkItem> &it
         cls[i] = item_class(ctx, items[i]);
         if (cls[i] >= 0) ncls[cls[i]]++;
     }
+    // within a launch, the largest clusters first: workgroups take items in
+    // list order, so the last ones to start are the cheapest (a shorter tail)
+    auto largest_first = [&](std::vector<WorkItem> &v) {
+        std::stable_sort(v.begin(), v.end(), [&](const WorkItem &x, const WorkItem &y) {
+            const ClusterMeta &a = ctx->meta[x.cluster], &b = ctx->meta[y.cluster];
+            return (int64_t)a.ns + a.nh + a.nnzVT > (int64_t)b.ns + b.nh + b.nnzVT;
+        });
+    };
     std::vector<WorkItem> order;
     order.reserve(n);
-    for (int c = 0; c < ncl; ++c)
+    for (int c = 0; c < ncl; ++c) {
+        std::vector<WorkItem> part;
         for (int i = 0; i < n; ++i)
-            if (cls[i] == c) order.push_back(items[i]);
+            if (cls[i] == c) part.push_back(items[i]);
+        largest_first(part);
+        order.insert(order.end(), part.begin(), part.end());
+    }
     std::vector<WorkItem> glob;
     for (int i = 0; i < n; ++i)
         if (cls[i] < 0) glob.push_back(items[i]);
+    largest_first(glob);
     n_glob = (int)glob.size();
     order.insert(order.end(), glob.begin(), glob.end());
     wsb = workspace_bytes(ctx, glob, nullptr);

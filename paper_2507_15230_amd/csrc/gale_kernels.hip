@@ -166,14 +166,15 @@ __device__ __forceinline__ void cswap_u(uint32_t &x, uint32_t &y) {
     y = hi;
 }
 
-// Sort 32 registers ascending (bitonic network).
-__device__ __forceinline__ void sort32(uint32_t (&v)[32]) {
+// Sort N registers ascending (bitonic network, N a power of two).
+template <int N>
+__device__ __forceinline__ void sort_regs(uint32_t (&v)[N]) {
 #pragma unroll
-    for (int k = 2; k <= 32; k <<= 1) {
+    for (int k = 2; k <= N; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
 #pragma unroll
-            for (int i = 0; i < 32; ++i) {
+            for (int i = 0; i < N; ++i) {
                 const int l = i ^ j;
                 if (l > i) {
                     if ((i & k) == 0)
@@ -363,7 +364,7 @@ template <int B, bool kL, bool kH>
 __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, const WorkItem &it, const ClusterMeta &m, const Plan &pl,
                               char *smem, char *ws) {
     using PosT = typename std::conditional<kL, uint16_t, int32_t>::type;
-    using LidT = typename std::conditional<kL, uint16_t, int32_t>::type;
+    using LidT = typename std::conditional<kL || kH, uint16_t, int32_t>::type;
 
     __shared__ int s_status;
     __shared__ int s_fail;
@@ -876,29 +877,35 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
         if ((mask & kRelVT) && vt_ok) {
             int32_t *buf = reinterpret_cast<int32_t *>(smem + pl.lt);
             const int bcap = kL ? (int)((pl.rix - pl.lt) / 4) : 0;
-            // rows of at most 32 entries: one thread each, in registers;
-            // longer rows: the wave of the row's thread, after its short rows
-            auto sort_short = [&](int r, int32_t *dst) {
+            // rows of at most 32 entries: one thread each, in registers, with
+            // a network of 8, 16 or 32 for the wave's longest such row; longer
+            // rows: the wave of the row's thread, after its short rows
+            auto sort_short = [&](auto ntag, int r, int32_t *dst) {
+                constexpr int N = decltype(ntag)::value;
                 const int s0 = cnt[r], n = cnt[r + 1] - s0;
-                uint32_t v[32];
+                uint32_t v[N];
 #pragma unroll
-                for (int i = 0; i < 32; ++i)
+                for (int i = 0; i < N; ++i)
                     v[i] = i < n ? (uint32_t)(idg[lvt[s0 + i]] & kIdMask) : 0xFFFFFFFFu;
-                sort32(v);
+                sort_regs<N>(v);
 #pragma unroll
-                for (int i = 0; i < 32; ++i)
+                for (int i = 0; i < N; ++i)
                     if (i < n) dst[i] = (int32_t)v[i];
             };
             // rows [rb, rb + B) with row rb + tid for this thread; dst_of(r)
             // is where row r's sorted list goes
             auto sort_rows = [&](int rb, int re, auto dst_of) {
                 const int r = rb + tid;
-                bool lng = false;
-                if (r < re) {
-                    if (cnt[r + 1] - cnt[r] <= 32)
-                        sort_short(r, dst_of(r));
+                const int n = r < re ? cnt[r + 1] - cnt[r] : -1;
+                const bool shrt = n >= 0 && n <= 32, lng = n > 32;
+                const unsigned long long over16 = __ballot(shrt && n > 16), over8 = __ballot(shrt && n > 8);
+                if (shrt) {
+                    if (over16)
+                        sort_short(std::integral_constant<int, 32>{}, r, dst_of(r));
+                    else if (over8)
+                        sort_short(std::integral_constant<int, 16>{}, r, dst_of(r));
                     else
-                        lng = true;
+                        sort_short(std::integral_constant<int, 8>{}, r, dst_of(r));
                 }
                 unsigned long long bal = __ballot(lng);
                 while (bal) {

@@ -239,7 +239,8 @@ GALE_HD Plan lds_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32
 // Global path with its most used arrays in LDS (a workgroup of this path
 // fills its compute unit's registers, so its LDS is otherwise idle): the face
 // table (32-bit cells) and the lower-cluster bits while TT runs; the row
-// index, row local ids, VT counts and VV bitmaps while VT / VV run.  The
+// index and row local ids (uint16: at most 65535 local vertices), VT counts
+// and VV bitmaps while VT / VV run.  The
 // partner cells and the local VT lists stay in the workspace slice (win and
 // lvt are offsets there, both from its start since TT is finished first),
 // and the stream is read from global memory.  bytes is the LDS used.
@@ -261,8 +262,8 @@ GALE_HD Plan hyb_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32
     const int64_t tt_end = p.ht + 4 * h;
     p.W = (m.L + 31) / 32;
     p.rix = 0;
-    p.rowl = p.rix + (v ? align16((int64_t)m.L * 4) : 0);
-    p.cnt = p.rowl + (v ? align16((int64_t)m.nV * 4) : 0);
+    p.rowl = p.rix + (v ? align16((int64_t)m.L * 2) : 0);
+    p.cnt = p.rowl + (v ? align16((int64_t)m.nV * 2) : 0);
     p.wbm = p.cnt + (v ? align16(((int64_t)m.nV + 1) * 4) : 0);
     p.G = 16;
     int64_t v_end = p.wbm + (vv ? align16((int64_t)(block_threads / 16) * p.W * 4) : 0);
@@ -273,7 +274,7 @@ GALE_HD Plan hyb_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32
     p.lvl = v_end;
     p.bytes = tt_end > v_end ? tt_end : v_end;
     const bool tt_ok = !tt || (h >= 64 && p.P <= kMaxFacePasses / 2);
-    const bool v_ok = !v || v_end <= budget;
+    const bool v_ok = !v || (v_end <= budget && m.L <= 65535);
     p.ok = (tt_ok && v_ok) ? 1 : 0;
     return p;
 }
