@@ -36,7 +36,7 @@ import numpy as np
 __all__ = [
     "Mesh", "kuhn_grid", "morton_keys", "clusters_fixed", "clusters_lognormal",
     "refine", "grid_mesh", "refined_mesh", "config", "CONFIGS",
-    "cube", "fig1_toy", "fig4_example", "single_tet", "random_small", "fans", "gauss_field",
+    "cube", "fig1_toy", "fig4_example", "single_tet", "random_small", "fans", "nonmanifold", "gauss_field",
 ]
 
 
@@ -411,6 +411,32 @@ def fans(ks=(16, 32, 33, 64, 65, 128, 129, 200, 300, 520), nclusters: int = 6, s
     tets, cluster, _, _ = _permute(rng, tets, cluster, None, None)
     return Mesh(tets=np.ascontiguousarray(tets), cluster=cluster, nclusters=nclusters,
                 meta={"kind": "fans", "ks": list(ks), "seed": seed})
+
+
+def nonmanifold(n: int = 5, fins: int = 6, dups: int = 3, nclusters: int = 3, seed: int = 0) -> Mesh:
+    """Faces shared by more than two tetrahedra: the n^3 Kuhn lattice plus
+    `fins` tetrahedra (a, b, c, x), each on a face (a, b, c) of a random
+    lattice tetrahedron with a new vertex x, and `dups` copies of random
+    lattice tetrahedra (same four vertices, new ids).  Random cluster labels,
+    then random vertex and tetrahedron ids.  Draw order: fin tetrahedra, fin
+    faces, duplicated tetrahedra, cluster labels, vperm, tperm."""
+    rng = np.random.default_rng(seed)
+    _, tets = kuhn_grid(n)
+    nv0 = n ** 3
+    ft = rng.choice(tets.shape[0], size=fins, replace=False)
+    fk = rng.integers(0, 4, size=fins)
+    extra = []
+    for i, (t, k) in enumerate(zip(ft, fk)):
+        face = [int(v) for j, v in enumerate(tets[t]) if j != k]
+        extra.append(face + [nv0 + i])
+    dt = rng.choice(tets.shape[0], size=dups, replace=False)
+    extra += [[int(v) for v in tets[t]] for t in dt]
+    tets = np.concatenate([tets, np.array(extra, dtype=np.int32).reshape(-1, 4)]).astype(np.int32)
+    nv = nv0 + fins
+    cluster = rng.integers(0, nclusters, size=nv).astype(np.int32)
+    tets, cluster, _, _ = _permute(rng, tets, cluster, None, None)
+    return Mesh(tets=np.ascontiguousarray(tets), cluster=cluster, nclusters=nclusters,
+                meta={"kind": "nonmanifold", "n": n, "fins": fins, "dups": dups, "seed": seed})
 
 
 def random_small(seed: int, n: int = 4, nclusters: int = 5, drop: float = 0.3,

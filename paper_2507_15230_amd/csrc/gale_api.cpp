@@ -135,7 +135,8 @@ int64_t workspace_bytes(const gale_ctx *ctx, const std::vector<WorkItem> &items,
     for (const WorkItem &it : items) {
         if (item_class(ctx, it) < 0) {
             const Plan gp = ws_plan(ctx->meta[it.cluster], it.mask, ctx->block_threads);
-            need = std::max<int64_t>(need, gp.bytes);
+            const Plan hp = hyb_plan(ctx->meta[it.cluster], it.mask, ctx->glob_lds, ctx->block_threads);
+            need = std::max<int64_t>(need, hp.ok ? hp.ws_bytes : gp.bytes);
             ++ng;
         }
     }

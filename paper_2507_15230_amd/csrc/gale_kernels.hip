@@ -451,8 +451,18 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
         uint32_t *ht32 = reinterpret_cast<uint32_t *>(ht);
         const int H = pl.H;
         const int cap = it.cap_tt;
-        const int win_words = kL ? 2 * nT : 4 * nT;  // 4 cells per row
-        const int ht_words = kL ? H / 2 : H;
+        const int win_words = kL ? 2 * nT : (kH ? 8 * nT : 4 * nT);  // 4 cells per row
+        const int ht_words = kL ? H / 2 : (kH ? 2 * H : H);
+        // hybrid path: 64-bit cells that hold the face itself, so that a probe
+        // step never reads the holder from global memory:
+        //   bits 0..19 stream position + 1, 20..21 the holder's face index,
+        //   22..63 the face's sorted local ids (14 bits each)
+        unsigned long long *ht64 = reinterpret_cast<unsigned long long *>(hot + pl.ht);
+        // hybrid path: 64-bit partner cells that a mark adds (position + 1) +
+        // 2^32 to, without waiting for the old value; a cell marked once holds
+        // its partner below bit 32, a high half above 1 means a third
+        // tetrahedron on the face (seen when the rows are read)
+        unsigned long long *win64 = reinterpret_cast<unsigned long long *>(base + pl.win);
 
         using Ins = std::integral_constant<bool, true>;
         using Look = std::integral_constant<bool, false>;
@@ -513,29 +523,61 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                     left = H + 2;  // a failed swap re-reads its cell; each cell changes once
                 };
                 if (todo) start();
-                while (todo) {
-                    uint32_t w;
-                    const uint32_t c = CL::read(ht, idx, w);
-                    const int q = c == 0u ? 0 : (int)c - 1;
-                    // the holder's face that is {fa, fb, fc}, if any (a tetrahedron
-                    // meets its own earlier faces on the way: skip them)
-                    const int kq = face_index(tet(q), fa, fb, fc);
-                    const bool hit = c != 0u && q != p && kq >= 0;
-                    bool stop = hit || (c == 0u && !kIns);
-                    if (kIns && c == 0u) stop = CL::try_set(ht, idx, w, (uint32_t)p + 1u);
-                    if (hit) {
-                        bool bad = CL::mark(win, 4 * (uint32_t)q + kq, (uint32_t)p + 1u);
-                        if (kIns) bad |= CL::mark(win, 4 * (uint32_t)p + k, c);
-                        if (bad) s_fail = 1;
+                if constexpr (kH) {
+                    while (todo) {
+                        const unsigned long long key = (unsigned long long)fa | (unsigned long long)fb << 14 |
+                                                       (unsigned long long)fc << 28;
+                        const unsigned long long w = __atomic_load_n(ht64 + idx, __ATOMIC_RELAXED);
+                        const bool used = w != 0ull;
+                        const uint32_t c = (uint32_t)(w & 0xFFFFFull);
+                        const int q = (int)c - 1;
+                        const bool hit = used && (w >> 22) == key && q != p;
+                        bool stop = hit || (!used && !kIns);
+                        if (kIns && !used) {
+                            const unsigned long long mine = (unsigned long long)(p + 1) |
+                                                            (unsigned long long)k << 20 | key << 22;
+                            stop = atomicCAS(ht64 + idx, 0ull, mine) == 0ull;
+                        }
+                        if (hit) {
+                            const int kq = (int)((w >> 20) & 3ull);
+                            (void)atomicAdd(win64 + 4 * (uint32_t)q + kq, (1ull << 32) | (unsigned long long)(p + 1));
+                            if (kIns) (void)atomicAdd(win64 + 4 * (uint32_t)p + k, (1ull << 32) | (unsigned long long)c);
+                        }
+                        if (used && !hit) idx = idx + 1 == (uint32_t)H ? 0u : idx + 1;
+                        if (--left == 0 && !stop) {
+                            if (kIns) s_full = 1;
+                            stop = true;
+                        }
+                        if (stop) {
+                            todo &= todo - 1u;
+                            if (todo) start();
+                        }
                     }
-                    if (c != 0u && !hit) idx = idx + 1 == (uint32_t)H ? 0u : idx + 1;
-                    if (--left == 0 && !stop) {
-                        if (kIns) s_full = 1;
-                        stop = true;
-                    }
-                    if (stop) {
-                        todo &= todo - 1u;
-                        if (todo) start();
+                } else {
+                    while (todo) {
+                        uint32_t w;
+                        const uint32_t c = CL::read(ht, idx, w);
+                        const int q = c == 0u ? 0 : (int)c - 1;
+                        // the holder's face that is {fa, fb, fc}, if any (a tetrahedron
+                        // meets its own earlier faces on the way: skip them)
+                        const int kq = face_index(tet(q), fa, fb, fc);
+                        const bool hit = c != 0u && q != p && kq >= 0;
+                        bool stop = hit || (c == 0u && !kIns);
+                        if (kIns && c == 0u) stop = CL::try_set(ht, idx, w, (uint32_t)p + 1u);
+                        if (hit) {
+                            bool bad = CL::mark(win, 4 * (uint32_t)q + kq, (uint32_t)p + 1u);
+                            if (kIns) bad |= CL::mark(win, 4 * (uint32_t)p + k, c);
+                            if (bad) s_fail = 1;
+                        }
+                        if (c != 0u && !hit) idx = idx + 1 == (uint32_t)H ? 0u : idx + 1;
+                        if (--left == 0 && !stop) {
+                            if (kIns) s_full = 1;
+                            stop = true;
+                        }
+                        if (stop) {
+                            todo &= todo - 1u;
+                            if (todo) start();
+                        }
                     }
                 }
             }
@@ -570,7 +612,8 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
         PHASE_MARK(1);
         // tetrahedron ids: from a copy over the face table when it fits (LDS)
         int32_t *idl = reinterpret_cast<int32_t *>(ht);
-        const bool ids_lds = (kL || kH) && (int64_t)sizeof(CT) * H >= 4 * (int64_t)ntot;
+        const int64_t ht_bytes = (int64_t)(kH ? 8 : sizeof(CT)) * H;
+        const bool ids_lds = (kL || kH) && ht_bytes >= 4 * (int64_t)ntot;
         if (ids_lds) {
             for (int i = tid; i < ntot; i += B) idl[i] = idg[i];
             __syncthreads();
@@ -585,8 +628,24 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                 int n0 = 0x7fffffff, n1 = 0x7fffffff, n2 = 0x7fffffff, n3 = 0x7fffffff;
                 int c = 0;
                 if (r < nT) {
-                    const uint32_t w0 = CL::get(win, 4 * r), w1 = CL::get(win, 4 * r + 1);
-                    const uint32_t w2 = CL::get(win, 4 * r + 2), w3 = CL::get(win, 4 * r + 3);
+                    uint32_t w0, w1, w2, w3;
+                    if constexpr (kH) {
+                        unsigned long long x[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            x[j] = __hip_atomic_load(win64 + 4 * r + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const bool twice = (x[0] >> 32) > 1 || (x[1] >> 32) > 1 || (x[2] >> 32) > 1 || (x[3] >> 32) > 1;
+                        if (twice) s_fail = 1;  // the rows are built again by exhaustive pairing
+                        w0 = twice ? 0u : (uint32_t)x[0];
+                        w1 = twice ? 0u : (uint32_t)x[1];
+                        w2 = twice ? 0u : (uint32_t)x[2];
+                        w3 = twice ? 0u : (uint32_t)x[3];
+                    } else {
+                        w0 = CL::get(win, 4 * r);
+                        w1 = CL::get(win, 4 * r + 1);
+                        w2 = CL::get(win, 4 * r + 2);
+                        w3 = CL::get(win, 4 * r + 3);
+                    }
                     if (w0 != 0u) n0 = id_of(w0 - 1) & kIdMask;
                     if (w1 != 0u) n1 = id_of(w1 - 1) & kIdMask;
                     if (w2 != 0u) n2 = id_of(w2 - 1) & kIdMask;
@@ -615,8 +674,11 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                 }
                 ecarry += tot;
             }
-        } else {
+        }
+        __syncthreads();
+        if (s_fail != 0) {
             // exhaustive pairing (non-manifold faces); rows are positions 0..nT-1
+            ecarry = 0;
             if (tid == 0) s_status |= kStTTFallback;
             auto tet_any = [&](int q) -> int4 { return q < nT ? tet(q) : tet_global(q); };
             for (int r0 = 0; r0 < nT; r0 += B) {
@@ -673,6 +735,7 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
         LidT *rowl = reinterpret_cast<LidT *>(hot + pl.rowl);
         int32_t *cnt = reinterpret_cast<int32_t *>(hot + pl.cnt);
         PosT *lvt = reinterpret_cast<PosT *>(base + pl.lvt);
+        ushort4 *lv4 = reinterpret_cast<ushort4 *>(ws + (kH ? pl.lv4 : 0));  // hybrid path only
         uint32_t *wbm = reinterpret_cast<uint32_t *>(hot + pl.wbm);
         constexpr LidT kNoRow = (LidT)-1;
 
@@ -732,10 +795,25 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
             for (int p = tid; p < ns; p += B) {
                 const int4 t = tet(p);
                 const LidT r0 = rix[t.x], r1 = rix[t.y], r2 = rix[t.z], r3 = rix[t.w];
-                if (r0 != kNoRow) lvt[atomicSub(&cnt[r0], 1) - 1] = (PosT)p;
-                if (r1 != kNoRow) lvt[atomicSub(&cnt[r1], 1) - 1] = (PosT)p;
-                if (r2 != kNoRow) lvt[atomicSub(&cnt[r2], 1) - 1] = (PosT)p;
-                if (r3 != kNoRow) lvt[atomicSub(&cnt[r3], 1) - 1] = (PosT)p;
+                if constexpr (kH) {
+                    // the entry's tetrahedron id (VT) and local ids (VV)
+                    const int32_t id = idg[p] & kIdMask;
+                    const ushort4 t4 = make_ushort4((uint16_t)t.x, (uint16_t)t.y, (uint16_t)t.z, (uint16_t)t.w);
+                    auto put = [&](LidT r) {
+                        const int j = atomicSub(&cnt[r], 1) - 1;
+                        lvt[j] = id;
+                        lv4[j] = t4;
+                    };
+                    if (r0 != kNoRow) put(r0);
+                    if (r1 != kNoRow) put(r1);
+                    if (r2 != kNoRow) put(r2);
+                    if (r3 != kNoRow) put(r3);
+                } else {
+                    if (r0 != kNoRow) lvt[atomicSub(&cnt[r0], 1) - 1] = (PosT)p;
+                    if (r1 != kNoRow) lvt[atomicSub(&cnt[r1], 1) - 1] = (PosT)p;
+                    if (r2 != kNoRow) lvt[atomicSub(&cnt[r2], 1) - 1] = (PosT)p;
+                    if (r3 != kNoRow) lvt[atomicSub(&cnt[r3], 1) - 1] = (PosT)p;
+                }
             }
         }
         __syncthreads();  // cnt[r] = start of row r's list, cnt[r+1] = its end
@@ -749,16 +827,16 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
         if ((mask & kRelVV) && vt_ok) {
             __shared__ int s_vc[2][B / 16];
             const int W = pl.W;
-            int32_t *lvl = reinterpret_cast<int32_t *>(base + pl.lvl);
+            // original ids of the local table: an LDS copy on the LDS path and,
+            // when it fits, on the hybrid path
+            const bool lvl_on = kL || (kH && pl.lvl >= 0);
+            int32_t *lvl = reinterpret_cast<int32_t *>(hot + (pl.lvl > 0 ? pl.lvl : 0));
             const int cap = it.cap_vv;
             for (int i = tid; i < (B / pl.G) * W; i += B) wbm[i] = 0u;
-            if constexpr (kL)
+            if (lvl_on)
                 for (int i = tid; i < L; i += B) lvl[i] = lvg[i] & kVidMask;
             __syncthreads();
-            auto orig = [&](int l) -> int32_t {
-                if constexpr (kL) return lvl[l];
-                else return lvg[l] & kVidMask;
-            };
+            auto orig = [&](int l) -> int32_t { return lvl_on ? lvl[l] : (lvg[l] & kVidMask); };
             int base_off = 0;
             auto rows_by = [&](auto gtag) {
                 constexpr int G = decltype(gtag)::value;
@@ -778,7 +856,13 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                     if (r < nV) {
                         const int self = rowl[r];
                         for (int i = cnt[r] + gl; i < cnt[r + 1]; i += G) {
-                            const int4 t = tet(lvt[i]);
+                            int4 t;
+                            if constexpr (kH) {
+                                const ushort4 q = lv4[i];
+                                t = make_int4(q.x, q.y, q.z, q.w);
+                            } else {
+                                t = tet(lvt[i]);
+                            }
                             mark(t.x, self);
                             mark(t.y, self);
                             mark(t.z, self);
@@ -880,13 +964,18 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
             // rows of at most 32 entries: one thread each, in registers, with
             // a network of 8, 16 or 32 for the wave's longest such row; longer
             // rows: the wave of the row's thread, after its short rows
+            // a local VT entry's tetrahedron id (the hybrid path stored it)
+            auto vt_key = [&](int e) -> int32_t {
+                if constexpr (kH) return lvt[e];
+                else return idg[lvt[e]] & kIdMask;
+            };
             auto sort_short = [&](auto ntag, int r, int32_t *dst) {
                 constexpr int N = decltype(ntag)::value;
                 const int s0 = cnt[r], n = cnt[r + 1] - s0;
                 uint32_t v[N];
 #pragma unroll
                 for (int i = 0; i < N; ++i)
-                    v[i] = i < n ? (uint32_t)(idg[lvt[s0 + i]] & kIdMask) : 0xFFFFFFFFu;
+                    v[i] = i < n ? (uint32_t)vt_key(s0 + i) : 0xFFFFFFFFu;
                 sort_regs<N>(v);
 #pragma unroll
                 for (int i = 0; i < N; ++i)
@@ -913,7 +1002,7 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                     bal &= bal - 1;
                     const int s0 = cnt[rr];
                     wave_sort(
-                        cnt[rr + 1] - s0, [&](int i) { return idg[lvt[s0 + i]] & kIdMask; }, dst_of(rr));
+                        cnt[rr + 1] - s0, [&](int i) { return vt_key(s0 + i); }, dst_of(rr));
                 }
             };
             for (int r = tid; r < nV; r += B) blk[lay.vt_off + r] = cnt[r];

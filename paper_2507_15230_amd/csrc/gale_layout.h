@@ -160,7 +160,9 @@ struct Plan {
     int32_t G;        // lanes per VV row group (16 or 32)
     int32_t pad;
     int64_t lt, win, lowb, ht, rix, rowl, cnt, lvt, wbm, lvl;
+    int64_t lv4;      // hybrid path: the local VT entries' tetrahedra (4 x uint16 each), in the workspace
     int64_t bytes;
+    int64_t ws_bytes; // hybrid path: workspace bytes used
 };
 
 GALE_HD int64_t align16(int64_t b) { return (b + 15) / 16 * 16; }
@@ -238,12 +240,18 @@ GALE_HD Plan lds_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32
 
 // Global path with its most used arrays in LDS (a workgroup of this path
 // fills its compute unit's registers, so its LDS is otherwise idle): the face
-// table (32-bit cells) and the lower-cluster bits while TT runs; the row
+// table (64-bit cells holding the face's local ids, so at most 16383 local
+// vertices when TT is requested) and the lower-cluster bits while TT runs; the row
 // index and row local ids (uint16: at most 65535 local vertices), VT counts
 // and VV bitmaps while VT / VV run.  The
 // partner cells and the local VT lists stay in the workspace slice (win and
 // lvt are offsets there, both from its start since TT is finished first),
-// and the stream is read from global memory.  bytes is the LDS used.
+// and the stream is read from global memory.  The local VT lists hold each
+// entry's original tetrahedron id (lvt, for VT) and its four local vertex ids
+// (lv4, for VV), written by the scatter, so that VT and VV read them in row
+// order instead of gathering through stream positions.  The local vertex
+// table's original ids are copied to LDS (lvl) when they fit, else lvl < 0.
+// bytes is the LDS used.
 GALE_HD Plan hyb_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32_t block_threads) {
     Plan p{};
     const bool tt = (mask & kRelTT) != 0;
@@ -253,13 +261,13 @@ GALE_HD Plan hyb_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32
     p.lvt = 0;
     p.lowb = 0;
     p.ht = tt ? align16((int64_t)((m.L + 31) / 32) * 4) : 0;
-    int64_t h = tt ? (budget - p.ht) / 4 : 0;
+    int64_t h = tt ? (budget - p.ht) / 8 : 0;
     const int64_t hmax = face_cells_max(m.nT);
     h = h > hmax ? hmax : h;
     h = h < 0 ? 0 : h;
     p.H = (int32_t)h;
     p.P = tt ? face_passes(m.nT, h) : 0;
-    const int64_t tt_end = p.ht + 4 * h;
+    const int64_t tt_end = p.ht + 8 * h;
     p.W = (m.L + 31) / 32;
     p.rix = 0;
     p.rowl = p.rix + (v ? align16((int64_t)m.L * 2) : 0);
@@ -271,9 +279,19 @@ GALE_HD Plan hyb_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32
         p.G = 32;
         v_end = p.wbm + (vv ? align16((int64_t)(block_threads / 32) * p.W * 4) : 0);
     }
-    p.lvl = v_end;
+    p.lvl = -1;
+    if (vv && v_end + align16((int64_t)m.L * 4) <= budget) {
+        p.lvl = v_end;
+        v_end += align16((int64_t)m.L * 4);
+    }
     p.bytes = tt_end > v_end ? tt_end : v_end;
-    const bool tt_ok = !tt || (h >= 64 && p.P <= kMaxFacePasses / 2);
+    p.lv4 = align16((int64_t)m.nnzVT * 4);
+    // TT: four 64-bit partner cells per row
+    const int64_t ws_tt = tt ? (int64_t)m.nT * 32 : 0;
+    const int64_t ws_v = v ? p.lv4 + (int64_t)m.nnzVT * 8 : 0;
+    p.ws_bytes = align16(ws_tt > ws_v ? ws_tt : ws_v);
+    const bool tt_ok = !tt || (h >= 64 && p.P <= kMaxFacePasses / 2 && m.L <= 16383 &&
+                               (int64_t)m.ns + m.nh < (1 << 20) - 1);
     const bool v_ok = !v || (v_end <= budget && m.L <= 65535);
     p.ok = (tt_ok && v_ok) ? 1 : 0;
     return p;

@@ -72,7 +72,9 @@ def brute_block(tets, cluster, k, rel, owner=None):
     out = []
     for t in rows:
         st = set(tets[t])
-        out.append([q for q in range(len(tets)) if q != t and len(st & set(tets[q])) == 3])
+        # a shared triangle = at least three shared vertices (a duplicate
+        # tetrahedron shares all four of its triangles)
+        out.append([q for q in range(len(tets)) if q != t and len(st & set(tets[q])) >= 3])
     return rows, out
 
 

@@ -401,3 +401,29 @@ def test_high_valence_rows(path):
         compare_all(ctx, m, orc, mask=1)
         if path == "global":
             assert ctx.stats()["global_path_blocks"] > 0
+
+
+@pytest.mark.parametrize("path", ["lds", "hybrid", "global", "plain"])
+def test_nonmanifold_faces(path):
+    """Faces of three tetrahedra (fins) and duplicated tetrahedra: the face
+    table finds them and the block's TT is built by exhaustive pairing, on the
+    LDS path, the hybrid global path (non-returning marks with counts), the
+    all-global path and the plain form."""
+    gale = _gale()
+    m = meshgen.nonmanifold(n=8, fins=12, dups=6, nclusters=2, seed=5)
+    _say("nonmanifold", path, m.nt)
+    orc = oracle.Oracle.of(m)
+    kw = {"lds": {}, "hybrid": {"lds_bytes": 12288}, "global": {"lds_bytes": 12288, "launch_classes": 8},
+          "plain": {}}[path]
+    with gale.Context(form="plain" if path == "plain" else "batched", **kw) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        compare_all(ctx, m, orc)
+        compare_all(ctx, m, orc, mask=4)
+        st = ctx.stats()
+        _say("global", st["global_path_blocks"], "hybrid", st["hybrid_path_blocks"], "exhaustive",
+             st["tt_exhaustive_blocks"])
+        assert st["tt_exhaustive_blocks"] > 0
+        if path == "hybrid":
+            assert st["hybrid_path_blocks"] > 0
+        if path == "global":
+            assert st["global_path_blocks"] > 0 and st["hybrid_path_blocks"] == 0

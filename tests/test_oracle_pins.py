@@ -352,3 +352,14 @@ def test_fan_closed_forms():
     # each VT list is the set of tetrahedra containing the vertex, ascending
     for v, l in vt.items():
         assert l == sorted(np.nonzero((m.tets == v).any(1))[0].tolist())
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_brute_force_nonmanifold(seed):
+    """Fins and duplicated tetrahedra (faces of three or four tetrahedra):
+    TT lists every tetrahedron sharing a face, a duplicate once."""
+    m = meshgen.nonmanifold(n=4, fins=5, dups=3, nclusters=3, seed=seed)
+    orc = oracle.Oracle.of(m)
+    assert brute_pin(orc, m)
+    blocks = pinlib.gather_all(orc.block, m.nclusters)
+    assert max(len(l) for l in blocks[REL_TT][1]) >= 4
