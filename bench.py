@@ -283,7 +283,8 @@ def main():
     if args.autotune == 1 or (args.autotune < 0 and args.config >= 3):
         log("autotune")
         chosen, cand = ctx.autotune(ids, 7, reps=2)
-        tuned = {"launch_classes": chosen, "candidates_ms": {str(k): v for k, v in cand.items()}}
+        tuned = {"launch_classes": chosen, "candidates_ms": {str(k): v for k, v in cand.items()},
+                 "global_cu_share": ctx.stats()["global_cu_share"]}
     use_graph = not args.no_graph
     graph = ctx.graph_create(ids, 7) if use_graph else None
 

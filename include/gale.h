@@ -136,6 +136,8 @@ typedef struct {
     uint64_t timed_launches;
     double   kernel_ms_total;
     uint64_t hybrid_path_blocks;    /* of global_path_blocks, those run with their most used arrays in LDS */
+    double   global_cu_share;       /* share of the CUs the global-path launch takes when LDS-path launch classes
+                                       run beside it (1 unless gale_autotune chose less) */
 } gale_stats;
 
 /* Create a context on cfg->device.  cfg may be NULL for defaults. */
@@ -168,7 +170,10 @@ gale_status gale_build(gale_ctx *ctx, const int32_t *cluster_ids, int32_t n, uin
  * value of gale_config.launch_classes (0, 2, 4, 6) builds the clusters
  * ids[0..n) with rel_mask in the BATCHED form, device only, once to warm up
  * and then `reps` times; the one with the shortest mean kernel time is kept
- * for the context's later batched work.  DIRECT mode with a mesh loaded; no
+ * for the context's later batched work.  When the request then runs both
+ * LDS-path classes and the global path, the share of the CUs the global
+ * launch takes (1, 0.8, 0.65, 0.5) is chosen the same way
+ * (gale_stats.global_cu_share).  DIRECT mode with a mesh loaded; no
  * other call may use the context meanwhile.  chosen_out (may be NULL)
  * receives the chosen value, ms_out (may be NULL; 4 doubles) the mean
  * milliseconds of each candidate in the order above.  EINVAL, ESTATE,

@@ -163,7 +163,7 @@ void destroy_ticket_events(Ticket *t) {
 
 // Launch items already uploaded in launch order: first the items of launch
 // class 0, then class 1, ... (ncls[c] each), then the n_glob items of the
-// global-workspace path.  PLAIN: one launch per item; BATCHED: one persistent
+// global-workspace path, with ncls[classes] workgroups (stage_items).  PLAIN: one launch per item; BATCHED: one persistent
 // launch per class and one for the global path, each with its own queue word
 // (d_queue[c], d_queue[classes]).  fork: run the launches on the auxiliary
 // streams, forked from and joined back into st (DIRECT mode); otherwise one
@@ -208,7 +208,16 @@ gale_status launch_batch(gale_ctx *ctx, int form, int32_t *d_out, int32_t *d_hdr
             if (ncls[c] > 0) ls.push_back({c, first, ncls[c]});
             first += ncls[c];
         }
-        if (n_glob > 0) ls.push_back({-1, first, n_glob});
+        // the global launch goes last, or first when it is given only a share
+        // of the CUs (its workgroups then take theirs at once and the classes
+        // fill the others)
+        const int gg = (int)ncls.size() > ncl ? ncls[ncl] : ctx->grid_glob;
+        if (n_glob > 0) {
+            if (gg < ctx->grid_glob)
+                ls.insert(ls.begin(), L{-1, first, n_glob});
+            else
+                ls.push_back({-1, first, n_glob});
+        }
         const bool use_aux = fork && ls.size() > 1 && ctx->aux.size() >= ls.size() - 1;
         if (kev) e = hipEventRecord(kev[0], st);
         if (use_aux && e == hipSuccess) e = hipEventRecord(ctx->fork_ev, st);
@@ -229,8 +238,7 @@ gale_status launch_batch(gale_ctx *ctx, int form, int32_t *d_out, int32_t *d_hdr
                 e = launch_persistent(a, true, lc.bt, std::min<int>(l.n, lc.grid), (size_t)lc.budget, s2);
             } else {
                 a.lds_budget = (int32_t)ctx->glob_lds;
-                e = launch_persistent(a, false, ctx->block_threads, std::min<int>(l.n, ctx->grid_glob),
-                                      (size_t)ctx->glob_lds, s2);
+                e = launch_persistent(a, false, ctx->block_threads, std::min<int>(l.n, gg), (size_t)ctx->glob_lds, s2);
             }
             ctx->n_launches++;
             if (e == hipSuccess && use_aux && li > 0) {
@@ -282,11 +290,17 @@ gale_status stage_items(gale_ctx *ctx, int form, const std::vector<WorkItem> &it
     largest_first(glob);
     n_glob = (int)glob.size();
     order.insert(order.end(), glob.begin(), glob.end());
+    // workgroups of the global launch: a global-path workgroup takes a whole
+    // CU; when LDS-path classes run beside it, it gets the context's share of
+    // the CUs (gale_autotune sets it), alone every CU
+    int glob_grid = ctx->grid_glob;
+    if (n_glob > 0 && n_glob < n) glob_grid = std::max(1, (int)(ctx->glob_share * ctx->grid_glob + 0.5));
+    ncls.push_back(glob_grid);
     wsb = workspace_bytes(ctx, glob, nullptr);
     ctx->n_global_blocks += n_glob;
     for (const WorkItem &it : glob)
         if (hyb_plan(ctx->meta[it.cluster], it.mask, ctx->glob_lds, ctx->block_threads).ok) ctx->n_hybrid_blocks++;
-    const int slots = form == GALE_FORM_PLAIN ? 1 : std::min<int>(std::max(n_glob, 1), ctx->grid_glob);
+    const int slots = form == GALE_FORM_PLAIN ? 1 : std::min<int>(std::max(n_glob, 1), glob_grid);
     dev_items = ctx->dev_pool.acquire((size_t)n * sizeof(WorkItem) + 64, &e);
     dev_hdr = ctx->dev_pool.acquire((size_t)n * 32 + 64, &e);
     host_items = ctx->pin_pool.acquire((size_t)n * sizeof(WorkItem) + 64, &e);
@@ -1001,11 +1015,8 @@ gale_status gale_autotune(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t
     }
     int best = -1;
     gale_status st = GALE_OK;
-    for (int ci = 0; ci < 4 && st == GALE_OK; ++ci) {
-        {
-            std::lock_guard<std::mutex> g(ctx->direct_mu);
-            setup_classes(ctx, candidates[ci]);
-        }
+    // mean kernel milliseconds of the request under the current settings
+    auto time_it = [&]() -> double {
         for (int r = 0; r <= reps && st == GALE_OK; ++r) {
             if (r == 1) {
                 std::lock_guard<std::mutex> g(ctx->direct_mu);
@@ -1018,12 +1029,51 @@ gale_status gale_autotune(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t
             if (tk) (void)gale_release(ctx, tk);
         }
         std::lock_guard<std::mutex> g(ctx->direct_mu);
-        ms[ci] = ctx->n_timed ? ctx->kernel_ms / (double)ctx->n_timed : 0.0;
+        return ctx->n_timed ? ctx->kernel_ms / (double)ctx->n_timed : 0.0;
+    };
+    const double saved_share = ctx->glob_share;
+    ctx->glob_share = 1.0;
+    for (int ci = 0; ci < 4 && st == GALE_OK; ++ci) {
+        {
+            std::lock_guard<std::mutex> g(ctx->direct_mu);
+            setup_classes(ctx, candidates[ci]);
+        }
+        ms[ci] = time_it();
         if (st == GALE_OK && (best < 0 || ms[ci] < ms[best])) best = ci;
     }
     {
         std::lock_guard<std::mutex> g(ctx->direct_mu);
         setup_classes(ctx, best >= 0 ? candidates[best] : ctx->cfg.launch_classes);
+    }
+    // then the global launch's share of the CUs, when the request runs both
+    // LDS-path classes and the global path
+    if (st == GALE_OK) {
+        int nglob = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            if (ids[i] < 0 || ids[i] >= ctx->ncl) continue;
+            WorkItem it{};
+            it.cluster = ids[i];
+            it.mask = mask;
+            nglob += item_class(ctx, it) < 0;
+        }
+        if (nglob > 0 && nglob < n) {
+            const double shares[3] = {0.8, 0.65, 0.5};
+            double best_ms = ms[best];
+            double best_share = 1.0;
+            for (int si = 0; si < 3 && st == GALE_OK; ++si) {
+                ctx->glob_share = shares[si];
+                const double t = time_it();
+                if (st == GALE_OK && t < best_ms) {
+                    best_ms = t;
+                    best_share = shares[si];
+                }
+            }
+            ctx->glob_share = best_share;
+        }
+    }
+    if (st != GALE_OK) ctx->glob_share = saved_share;
+    {
+        std::lock_guard<std::mutex> g(ctx->direct_mu);
         ctx->n_timed = saved_n;
         ctx->kernel_ms = saved_ms;
     }
@@ -1068,6 +1118,7 @@ gale_status gale_get_stats(gale_ctx *ctx, gale_stats *out) {
     out->overflow_reruns = ctx->n_overflow;
     out->global_path_blocks = ctx->n_global_blocks;
     out->hybrid_path_blocks = ctx->n_hybrid_blocks;
+    out->global_cu_share = ctx->glob_share;
     out->tt_exhaustive_blocks = ctx->n_tt_exhaustive;
     out->entries_delivered = ctx->n_delivered;
     out->bytes_d2h = ctx->n_bytes_d2h;

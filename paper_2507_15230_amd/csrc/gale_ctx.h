@@ -152,6 +152,9 @@ struct gale_ctx {
     // dynamic LDS of a global-path workgroup (the hybrid form's arrays), 0
     // when the global path keeps every array in global memory
     int64_t glob_lds = 0;
+    // share of the CUs the global launch takes when LDS-path classes run
+    // beside it (gale_autotune)
+    double glob_share = 1.0;
     // workgroup shapes for LDS-path clusters, largest LDS first; a cluster
     // takes the last (smallest) one its working set fits
     struct LaunchClass {

@@ -54,6 +54,7 @@ class GaleStats(C.Structure):
         ("lat_max_us", C.c_double), ("lat_count", C.c_uint64),
         ("stage_queue_us", C.c_double), ("stage_build_us", C.c_double), ("stage_copy_us", C.c_double),
         ("timed_launches", C.c_uint64), ("kernel_ms_total", C.c_double), ("hybrid_path_blocks", C.c_uint64),
+        ("global_cu_share", C.c_double),
     ]
 
 
@@ -258,7 +259,8 @@ class Context:
 
     def autotune(self, cluster_ids, mask: int = 7, reps: int = 2):
         """Time the launch-class candidates (0, 2, 4, 6) on this request and keep
-        the fastest; returns (chosen, {candidate: mean ms})."""
+        the fastest (then the global launch's share of the CUs, see
+        stats()["global_cu_share"]); returns (chosen, {candidate: mean ms})."""
         a = np.ascontiguousarray(cluster_ids, np.int32)
         p = a.ctypes.data_as(C.POINTER(C.c_int32))
         chosen = C.c_int32()
