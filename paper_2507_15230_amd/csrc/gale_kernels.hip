@@ -1,38 +1,44 @@
 // gale_kernels.hip -- per-cluster VT / VV / TT builders for gfx950.
 //
 // One workgroup builds every requested relation of one cluster (the paper
-// assigns one GPU block per segment, Section 4.6).  The cluster's stream of
-// star and halo tetrahedra is read from HBM once and, when the working set
-// fits, staged in LDS as 4 x uint16 local vertex ids; all later passes read it
-// from LDS.  Working arrays live in LDS (fast path) or, for clusters too large
-// for the LDS budget, in a per-workgroup slice of global memory (same
-// algorithm, 32-bit types).
+// assigns one GPU block per segment, Section 4.6); a persistent launch takes
+// clusters from a device queue.  The working arrays of a cluster live in one
+// of three places, chosen per cluster by the host with the plan functions of
+// gale_layout.h:
+//   LDS path     everything in LDS, the stream staged there as 4 x uint16
+//                local vertex ids; 16-bit ids, positions and cells;
+//   hybrid path  (global path, LDS plan too large) the face table, lower-
+//                cluster bits, row index, row ids, VT counts and VV bitmaps
+//                in LDS, the partner cells and local VT lists in a
+//                per-workgroup slice of global memory, the stream read from
+//                global memory;
+//   global path  every array in the workspace slice (32-bit types).
 //
-// VT and VV are read from one structure: the local VT relation of every
-// vertex of the cluster's local table (count per vertex with LDS atomics,
-// inclusive scan, scatter of stream positions with atomic decrements).  No
-// global atomics are used (the paper's VT kernel is limited by atomics on one
-// vertex, Appendix A.1).
+// VT and VV are read from one structure: the local VT relation of every row
+// of the cluster (count per vertex with LDS atomics, scan, scatter with
+// atomic decrements).  No global atomics on the VT counts (the paper's VT
+// kernel is limited by atomics on one vertex, Appendix A.1).
 //
 // VT (Section 4.6: iterate the segment's tetrahedra, take the vertices in the
-// segment, relate them): a row's list, sorted; stream order is tetrahedron id
-// order, so the sorted positions are the canonical row.
+// segment, relate them): a row's list sorted by original tetrahedron id, by
+// register sorting networks (a thread per row up to 32 entries, a wave per
+// row beyond).
 //
 // VV (Algorithm 1: for each tetrahedron and each of its vertices in the
-// segment, relate the other three, without duplicates): a wave takes one row
-// at a time and sets bits in its own LDS bitmap over the local vertex table;
-// the table is in original id order, so reading the set bits in word order
-// yields the row sorted and duplicate-free.  This replaces the paper's
-// fixed-width -1 initialised matrix and atomicPush (Algorithm 2), whose output
-// order depends on thread arrival.  Counts first, then emission, so offsets
-// are known before any entry is written.
+// segment, relate the other three, without duplicates): a group of 16 or 32
+// lanes takes one row at a time and sets bits in its own LDS bitmap over the
+// local vertex table; the table is in original id order, so reading the set
+// bits in word order yields the row sorted and duplicate-free.  This replaces
+// the paper's fixed-width -1 initialised matrix and atomicPush (Algorithm 2),
+// whose output order depends on thread arrival.  Counts first, then emission,
+// so offsets are known before any entry is written.
 //
 // TT (two tetrahedra are adjacent iff they share a triangle, Section 2.2):
-// an LDS hash table keyed by the triangle (its three local ids, sorted).
+// a hash table keyed by the triangle (its three local ids, sorted).
 // Internal tetrahedra insert their four faces; the second to insert a face
-// pairs the two and writes each into the other's partner slot for that face.
+// pairs the two and writes each into the other's partner cell for that face.
 // The remaining stream tetrahedra then look their faces up and write
-// themselves into the internal partner's slot.  A face met a third time
+// themselves into the internal partner's cell.  A face met a third time
 // (non-manifold) switches the cluster to exhaustive pairing.  When the table
 // is smaller than the faces, the faces are split by hash into passes.  TT
 // runs before the local VT is built and shares its LDS region.
@@ -961,14 +967,14 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
         if ((mask & kRelVT) && vt_ok) {
             int32_t *buf = reinterpret_cast<int32_t *>(smem + pl.lt);
             const int bcap = kL ? (int)((pl.rix - pl.lt) / 4) : 0;
-            // rows of at most 32 entries: one thread each, in registers, with
-            // a network of 8, 16 or 32 for the wave's longest such row; longer
-            // rows: the wave of the row's thread, after its short rows
             // a local VT entry's tetrahedron id (the hybrid path stored it)
             auto vt_key = [&](int e) -> int32_t {
                 if constexpr (kH) return lvt[e];
                 else return idg[lvt[e]] & kIdMask;
             };
+            // rows of at most 32 entries: one thread each, in registers, with
+            // a network of 8, 16 or 32 for the wave's longest such row; longer
+            // rows: the wave of the row's thread, after its short rows
             auto sort_short = [&](auto ntag, int r, int32_t *dst) {
                 constexpr int N = decltype(ntag)::value;
                 const int s0 = cnt[r], n = cnt[r + 1] - s0;
