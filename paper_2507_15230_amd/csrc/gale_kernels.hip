@@ -25,7 +25,7 @@
 // row beyond).
 //
 // VV (Algorithm 1: for each tetrahedron and each of its vertices in the
-// segment, relate the other three, without duplicates): a group of 16 or 32
+// segment, relate the other three, without duplicates): a group of 8, 16 or 32
 // lanes takes one row at a time and sets bits in its own LDS bitmap over the
 // local vertex table; the table is in original id order, so reading the set
 // bits in word order yields the row sorted and duplicate-free.  This replaces
@@ -824,14 +824,14 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
         }
         __syncthreads();  // cnt[r] = start of row r's list, cnt[r+1] = its end
         PHASE_MARK(3);
-        // ---- VV: one row per group of G lanes (16 or 32), in rounds of B/G
+        // ---- VV: one row per group of G lanes (8, 16 or 32), in rounds of B/G
         // rows.  The group marks the row's neighbours in its bitmap over the
         // local table; each lane takes a run of consecutive words (into
         // registers when they are few) and counts their bits; the round's
         // counts give every row its offset after one barrier; the row is then
         // emitted in word order, which is original id order.
         if ((mask & kRelVV) && vt_ok) {
-            __shared__ int s_vc[2][B / 16];
+            __shared__ int s_vc[2][B / 8];
             const int W = pl.W;
             // original ids of the local table: an LDS copy on the LDS path and,
             // when it fits, on the hybrid path
@@ -950,7 +950,8 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                     base_off += round_total;
                 }
             };
-            if (pl.G == 16) rows_by(std::integral_constant<int, 16>{});
+            if (pl.G == 8) rows_by(std::integral_constant<int, 8>{});
+            else if (pl.G == 16) rows_by(std::integral_constant<int, 16>{});
             else rows_by(std::integral_constant<int, 32>{});
             if (tid == 0) {
                 blk[lay.vv_off + nV] = base_off;

@@ -157,7 +157,7 @@ struct Plan {
     int32_t W;        // bitmap words per row
     int32_t H;        // face table cells
     int32_t P;        // face table passes (faces split by hash)
-    int32_t G;        // lanes per VV row group (16 or 32)
+    int32_t G;        // lanes per VV row group (8, 16 or 32)
     int32_t pad;
     int64_t lt, win, lowb, ht, rix, rowl, cnt, lvt, wbm, lvl;
     int64_t lv4;      // hybrid path: the local VT entries' tetrahedra (4 x uint16 each), in the workspace
@@ -228,8 +228,11 @@ GALE_HD Plan lds_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32
     p.P = tt ? face_passes(m.nT, h) : 0;
     const int64_t tt_end = p.ht + 2 * h;
     // VT / VV after the star tetrahedra (the halo holds no vertex of C); VV
-    // rows by groups of 16 lanes when their bitmaps fit, else 32
-    int64_t v_end = v_arrays(p, m, mask, align16((int64_t)m.ns * 8), 2, block_threads, 16);
+    // rows by groups of 8 lanes when their bitmaps fit and each lane keeps its
+    // run of bitmap words in registers (at most 64 words), else 16, else 32
+    const bool g8 = (m.L + 31) / 32 <= 64;
+    int64_t v_end = v_arrays(p, m, mask, align16((int64_t)m.ns * 8), 2, block_threads, g8 ? 8 : 16);
+    if (v_end > budget && g8) v_end = v_arrays(p, m, mask, align16((int64_t)m.ns * 8), 2, block_threads, 16);
     if (v_end > budget) v_end = v_arrays(p, m, mask, align16((int64_t)m.ns * 8), 2, block_threads, 32);
     p.bytes = tt_end > v_end ? tt_end : v_end;
     const bool tt_ok = !tt || (h >= 64 && p.P <= kMaxFacePasses / 2 && tt_end <= budget);
