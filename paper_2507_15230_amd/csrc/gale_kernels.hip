@@ -314,6 +314,13 @@ struct Cells<true> {
         const uint32_t old = (atomicOr(word(a, i), v << sh) >> sh) & 0xFFFFu;
         return old != 0u && old != v;
     }
+    __device__ static void mark_issue(T *a, uint32_t i, uint32_t v, uint32_t &w) {
+        w = atomicOr(word(a, i), v << ((i & 1) * 16));
+    }
+    __device__ static bool mark_bad(uint32_t i, uint32_t v, uint32_t w) {
+        const uint32_t old = (w >> ((i & 1) * 16)) & 0xFFFFu;
+        return old != 0u && old != v;
+    }
     __device__ static uint32_t get(const T *a, uint32_t i) { return a[i]; }
 };
 template <>
@@ -328,6 +335,8 @@ struct Cells<false> {
         const uint32_t old = atomicOr(a + i, v);
         return old != 0u && old != v;
     }
+    __device__ static void mark_issue(T *a, uint32_t i, uint32_t v, uint32_t &w) { w = atomicOr(a + i, v); }
+    __device__ static bool mark_bad(uint32_t, uint32_t v, uint32_t w) { return w != 0u && w != v; }
     __device__ static uint32_t get(const T *a, uint32_t i) { return a[i]; }
 };
 
@@ -571,8 +580,13 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                         bool stop = hit || (c == 0u && !kIns);
                         if (kIns && c == 0u) stop = CL::try_set(ht, idx, w, (uint32_t)p + 1u);
                         if (hit) {
-                            bool bad = CL::mark(win, 4 * (uint32_t)q + kq, (uint32_t)p + 1u);
-                            if (kIns) bad |= CL::mark(win, 4 * (uint32_t)p + k, c);
+                            // both marks issued before either old value is looked at
+                            uint32_t o1, o2 = 0u;
+                            const uint32_t v1 = (uint32_t)p + 1u, i1 = 4 * (uint32_t)q + kq, i2 = 4 * (uint32_t)p + k;
+                            CL::mark_issue(win, i1, v1, o1);
+                            if (kIns) CL::mark_issue(win, i2, c, o2);
+                            bool bad = CL::mark_bad(i1, v1, o1);
+                            if (kIns) bad |= CL::mark_bad(i2, c, o2);
                             if (bad) s_fail = 1;
                         }
                         if (c != 0u && !hit) idx = idx + 1 == (uint32_t)H ? 0u : idx + 1;
