@@ -852,7 +852,8 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
             const bool lvl_on = kL || (kH && pl.lvl >= 0);
             int32_t *lvl = reinterpret_cast<int32_t *>(hot + (pl.lvl > 0 ? pl.lvl : 0));
             const int cap = it.cap_vv;
-            for (int i = tid; i < (B / pl.G) * W; i += B) wbm[i] = 0u;
+            const int Wg = (int)vv_group_words(W);  // a group's bitmap, then its summary
+            for (int i = tid; i < (B / pl.G) * Wg; i += B) wbm[i] = 0u;
             if (lvl_on)
                 for (int i = tid; i < L; i += B) lvl[i] = lvg[i] & kVidMask;
             __syncthreads();
@@ -863,12 +864,20 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                 constexpr int NG = B / G;
                 constexpr int KMAX = 8;  // bitmap words a lane keeps in registers
                 const int grp = tid / G, gl = tid % G;
-                uint32_t *wb = wbm + (int64_t)grp * W;
+                uint32_t *wb = wbm + (int64_t)grp * Wg;
+                uint32_t *sb = wb + W;  // bit b of sb[s]: word 32 s + b has a bit set
                 const int K = (W + G - 1) / G;  // words per lane
                 const int wbeg = gl * K, wend = min(W, wbeg + K);
                 const bool in_regs = K <= KMAX;
+                // larger bitmaps: a lane takes a run of summary words (32 bitmap
+                // words each) and visits only the words marked in them
+                const int SW = (W + 31) / 32, SK = (SW + G - 1) / G;
+                const int sbeg = gl * SK, send = min(SW, sbeg + SK);
                 auto mark = [&](int v, int self) {
-                    if (v != self) atomicOr(&wb[v >> 5], 1u << (v & 31));
+                    if (v != self) {
+                        atomicOr(&wb[v >> 5], 1u << (v & 31));
+                        if (!in_regs) atomicOr(&sb[v >> 10], 1u << ((v >> 5) & 31));
+                    }
                 };
                 int par = 0;
                 for (int r0 = 0; r0 < nV; r0 += NG) {
@@ -904,7 +913,14 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                         for (int j = 0; j < KMAX; ++j)
                             if (wv[j]) wb[wbeg + j] = 0u;
                     } else {
-                        for (int w = wbeg; w < wend; ++w) n += __popc(wb[w]);
+                        for (int s = sbeg; s < send; ++s) {
+                            uint32_t sbits = sb[s];
+                            while (sbits) {
+                                const int b = __ffs(sbits) - 1;
+                                sbits &= sbits - 1u;
+                                n += __popc(wb[s * 32 + b]);
+                            }
+                        }
                     }
                     int c = n;
 #pragma unroll
@@ -945,9 +961,15 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                                 }
                             }
                         } else {
-                            for (int w = wbeg; w < wend; ++w) {
-                                uint32_t bits = wb[w];
-                                if (bits) {
+                            // the same run of summary words as counted, in word order
+                            for (int s = sbeg; s < send; ++s) {
+                                uint32_t sbits = sb[s];
+                                if (!sbits) continue;
+                                sb[s] = 0u;
+                                while (sbits) {
+                                    const int w = s * 32 + __ffs(sbits) - 1;
+                                    sbits &= sbits - 1u;
+                                    uint32_t bits = wb[w];
                                     wb[w] = 0u;
                                     if (fits) {
                                         while (bits) {
@@ -1115,7 +1137,7 @@ __device__ __attribute__((always_inline)) void process_item(const KArgs &a, cons
 // One work item per workgroup: item blockIdx.x.  Used for the per-cluster
 // (plain) form, one launch per (cluster, relation).
 template <int B, bool kL>
-__global__ __launch_bounds__(B) void gale_items_kernel(KArgs a) {
+__global__ __launch_bounds__(B, 4) void gale_items_kernel(KArgs a) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int i = blockIdx.x;
     if (i >= a.nitems) return;
@@ -1126,7 +1148,7 @@ __global__ __launch_bounds__(B) void gale_items_kernel(KArgs a) {
 // Persistent form: each workgroup takes the next item from the device work
 // queue until the list is exhausted (every workgroup reaches the exit test).
 template <int B, bool kL>
-__global__ __launch_bounds__(B) void gale_persistent_kernel(KArgs a) {
+__global__ __launch_bounds__(B, 4) void gale_persistent_kernel(KArgs a) {
     extern __shared__ __attribute__((aligned(16))) char smem[];
     __shared__ int s_idx;
     char *ws = a.ws ? a.ws + (int64_t)blockIdx.x * a.ws_stride : nullptr;

@@ -183,6 +183,10 @@ GALE_HD int32_t face_passes(int32_t nT, int64_t H) {
 // Face table cells kept per TT row at most (load about 1/3 on a closed region).
 GALE_HD int64_t face_cells_max(int32_t nT) { return 6 * (int64_t)nT + 64; }
 
+// Words of one VV row group: its bitmap over the local table (W words) and a
+// summary with one bit per bitmap word.
+GALE_HD int64_t vv_group_words(int64_t W) { return W + (W + 31) / 32; }
+
 // VT / VV arrays from byte offset off (cell: bytes of an id or position),
 // with one VV bitmap per group of vv_group lanes; returns the end.
 GALE_HD int64_t v_arrays(Plan &p, const ClusterMeta &m, uint32_t mask, int64_t off, int cell, int block_threads,
@@ -201,7 +205,7 @@ GALE_HD int64_t v_arrays(Plan &p, const ClusterMeta &m, uint32_t mask, int64_t o
     p.lvt = off;
     off += v ? align16((int64_t)m.nnzVT * cell) : 0;
     p.wbm = off;
-    off += vv ? align16(ngroups * (int64_t)p.W * 4) : 0;
+    off += vv ? align16(ngroups * vv_group_words(p.W) * 4) : 0;
     p.lvl = off;
     off += (vv && cell == 2) ? align16((int64_t)m.L * 4) : 0;
     return off;
@@ -277,10 +281,10 @@ GALE_HD Plan hyb_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32
     p.cnt = p.rowl + (v ? align16((int64_t)m.nV * 2) : 0);
     p.wbm = p.cnt + (v ? align16(((int64_t)m.nV + 1) * 4) : 0);
     p.G = 16;
-    int64_t v_end = p.wbm + (vv ? align16((int64_t)(block_threads / 16) * p.W * 4) : 0);
+    int64_t v_end = p.wbm + (vv ? align16((int64_t)(block_threads / 16) * vv_group_words(p.W) * 4) : 0);
     if (v_end > budget) {
         p.G = 32;
-        v_end = p.wbm + (vv ? align16((int64_t)(block_threads / 32) * p.W * 4) : 0);
+        v_end = p.wbm + (vv ? align16((int64_t)(block_threads / 32) * vv_group_words(p.W) * 4) : 0);
     }
     p.lvl = -1;
     if (vv && v_end + align16((int64_t)m.L * 4) <= budget) {
