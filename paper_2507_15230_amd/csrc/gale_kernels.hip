@@ -470,8 +470,8 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
         const int ht_words = kL ? H / 2 : (kH ? 2 * H : H);
         // hybrid path: 64-bit cells that hold the face itself, so that a probe
         // step never reads the holder from global memory:
-        //   bits 0..19 stream position + 1, 20..21 the holder's face index,
-        //   22..63 the face's sorted local ids (14 bits each)
+        //   bits 0..16 stream position + 1, 17..18 the holder's face index,
+        //   19..63 the face's sorted local ids (15 bits each)
         unsigned long long *ht64 = reinterpret_cast<unsigned long long *>(hot + pl.ht);
         // hybrid path: 64-bit partner cells that a mark adds (position + 1) +
         // 2^32 to, without waiting for the old value; a cell marked once holds
@@ -540,21 +540,21 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                 if (todo) start();
                 if constexpr (kH) {
                     while (todo) {
-                        const unsigned long long key = (unsigned long long)fa | (unsigned long long)fb << 14 |
-                                                       (unsigned long long)fc << 28;
+                        const unsigned long long key = (unsigned long long)fa | (unsigned long long)fb << 15 |
+                                                       (unsigned long long)fc << 30;
                         const unsigned long long w = __atomic_load_n(ht64 + idx, __ATOMIC_RELAXED);
                         const bool used = w != 0ull;
-                        const uint32_t c = (uint32_t)(w & 0xFFFFFull);
+                        const uint32_t c = (uint32_t)(w & 0x1FFFFull);
                         const int q = (int)c - 1;
-                        const bool hit = used && (w >> 22) == key && q != p;
+                        const bool hit = used && (w >> 19) == key && q != p;
                         bool stop = hit || (!used && !kIns);
                         if (kIns && !used) {
                             const unsigned long long mine = (unsigned long long)(p + 1) |
-                                                            (unsigned long long)k << 20 | key << 22;
+                                                            (unsigned long long)k << 17 | key << 19;
                             stop = atomicCAS(ht64 + idx, 0ull, mine) == 0ull;
                         }
                         if (hit) {
-                            const int kq = (int)((w >> 20) & 3ull);
+                            const int kq = (int)((w >> 17) & 3ull);
                             (void)atomicAdd(win64 + 4 * (uint32_t)q + kq, (1ull << 32) | (unsigned long long)(p + 1));
                             if (kIns) (void)atomicAdd(win64 + 4 * (uint32_t)p + k, (1ull << 32) | (unsigned long long)c);
                         }

@@ -167,7 +167,12 @@ struct Plan {
 
 GALE_HD int64_t align16(int64_t b) { return (b + 15) / 16 * 16; }
 
-constexpr int kMaxFacePasses = 16;
+// Face table passes: at most this many after doublings (then exhaustive
+// pairing); a plan starts with at most kLdsFacePasses (LDS path) or
+// kHybFacePasses (hybrid path).
+constexpr int kMaxFacePasses = 32;
+constexpr int kLdsFacePasses = 8;
+constexpr int kHybFacePasses = 12;
 
 // Face table passes for H cells: distinct faces are estimated at 2.5 per TT
 // row (a closed region has 2 plus half its boundary) at load 0.7; the kernel
@@ -239,7 +244,7 @@ GALE_HD Plan lds_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32
     if (v_end > budget && g8) v_end = v_arrays(p, m, mask, align16((int64_t)m.ns * 8), 2, block_threads, 16);
     if (v_end > budget) v_end = v_arrays(p, m, mask, align16((int64_t)m.ns * 8), 2, block_threads, 32);
     p.bytes = tt_end > v_end ? tt_end : v_end;
-    const bool tt_ok = !tt || (h >= 64 && p.P <= kMaxFacePasses / 2 && tt_end <= budget);
+    const bool tt_ok = !tt || (h >= 64 && p.P <= kLdsFacePasses && tt_end <= budget);
     const bool v_ok = !v || v_end <= budget;
     p.ok = (narrow && tt_ok && v_ok) ? 1 : 0;
     return p;
@@ -247,8 +252,9 @@ GALE_HD Plan lds_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32
 
 // Global path with its most used arrays in LDS (a workgroup of this path
 // fills its compute unit's registers, so its LDS is otherwise idle): the face
-// table (64-bit cells holding the face's local ids, so at most 16383 local
-// vertices when TT is requested) and the lower-cluster bits while TT runs; the row
+// table (64-bit cells holding the face's local ids and a stream position, so at
+// most 32767 local vertices and 131070 stream tetrahedra when TT is
+// requested) and the lower-cluster bits while TT runs; the row
 // index and row local ids (uint16: at most 65535 local vertices), VT counts
 // and VV bitmaps while VT / VV run.  The
 // partner cells and the local VT lists stay in the workspace slice (win and
@@ -297,8 +303,8 @@ GALE_HD Plan hyb_plan(const ClusterMeta &m, uint32_t mask, int64_t budget, int32
     const int64_t ws_tt = tt ? (int64_t)m.nT * 32 : 0;
     const int64_t ws_v = v ? p.lv4 + (int64_t)m.nnzVT * 8 : 0;
     p.ws_bytes = align16(ws_tt > ws_v ? ws_tt : ws_v);
-    const bool tt_ok = !tt || (h >= 64 && p.P <= kMaxFacePasses / 2 && m.L <= 16383 &&
-                               (int64_t)m.ns + m.nh < (1 << 20) - 1);
+    const bool tt_ok = !tt || (h >= 64 && p.P <= kHybFacePasses && m.L <= 32767 &&
+                               (int64_t)m.ns + m.nh < (1 << 17) - 1);
     const bool v_ok = !v || (v_end <= budget && m.L <= 65535);
     p.ok = (tt_ok && v_ok) ? 1 : 0;
     return p;
