@@ -82,6 +82,9 @@ typedef struct {
                                      placing its most used ones in LDS when they fit (used by tests). */
     void    *hip_stream;          /* borrowed hipStream_t for DIRECT mode work, or NULL for a library-owned stream.
                                      Must outlive the context. */
+    double   global_cu_share;     /* BATCHED form: share of the CUs (0 < s <= 1) the global-path launch takes when
+                                     LDS-path launch classes run beside it (it is then launched first); 0 = 1.
+                                     gale_autotune may change it. */
 } gale_config;
 
 /* A read-only view of one CSR block.  For gale_block the pointers are host

@@ -779,6 +779,8 @@ gale_status gale_create(const gale_config *cfg_in, gale_ctx **out) {
     if (cfg.form != GALE_FORM_PLAIN && cfg.form != GALE_FORM_BATCHED) return fail(GALE_EINVAL, "unknown form");
     if (cfg.block_threads != 0 && cfg.block_threads != 256 && cfg.block_threads != 512 && cfg.block_threads != 1024)
         return fail(GALE_EINVAL, "block_threads must be 256, 512 or 1024");
+    if (!(cfg.global_cu_share >= 0.0 && cfg.global_cu_share <= 1.0))
+        return fail(GALE_EINVAL, "global_cu_share must be in [0, 1]");
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || ndev <= 0) return fail(GALE_EDEVICE, "no HIP device");
@@ -787,6 +789,7 @@ gale_status gale_create(const gale_config *cfg_in, gale_ctx **out) {
     if (e != hipSuccess) return fail(GALE_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
     auto *ctx = new gale_ctx();
     ctx->cfg = cfg;
+    ctx->glob_share = cfg.global_cu_share > 0.0 ? cfg.global_cu_share : 1.0;
     ctx->dev_pool.pinned = false;
     ctx->pin_pool.pinned = true;
     hipDeviceProp_t prop;

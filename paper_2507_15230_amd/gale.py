@@ -27,6 +27,7 @@ class GaleConfig(C.Structure):
         ("device", C.c_int32), ("mode", C.c_int32), ("form", C.c_int32), ("block_threads", C.c_int32),
         ("lds_bytes", C.c_int32), ("max_inflight", C.c_int32), ("cache_budget_bytes", C.c_uint64),
         ("max_queue", C.c_int32), ("launch_classes", C.c_int32), ("hip_stream", C.c_void_p),
+        ("global_cu_share", C.c_double),
     ]
 
 
@@ -143,7 +144,7 @@ class Context:
 
     def __init__(self, device: int = 0, mode: str = "direct", form: str = "batched", block_threads: int = 0,
                  lds_bytes: int = 0, max_inflight: int = 0, cache_budget_bytes: int = 0, max_queue: int = 0,
-                 stream=None, launch_classes: int = 0):
+                 stream=None, launch_classes: int = 0, global_cu_share: float = 0.0):
         lib = load_library()
         self._lib = lib
         cfg = GaleConfig()
@@ -157,6 +158,7 @@ class Context:
         cfg.max_queue = max_queue
         cfg.launch_classes = launch_classes
         cfg.hip_stream = stream
+        cfg.global_cu_share = global_cu_share
         h = C.c_void_p()
         _check(lib.gale_create(C.byref(cfg), C.byref(h)), "gale_create")
         self._h = h

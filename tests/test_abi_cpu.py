@@ -68,6 +68,14 @@ def test_null_arguments_rejected():
     lib.gale_destroy(None)
 
 
+def test_create_rejects_bad_config_before_the_device():
+    from paper_2507_15230_amd import gale
+    for kw in ({"block_threads": 100}, {"global_cu_share": 1.5}, {"global_cu_share": -0.1}):
+        with pytest.raises(gale.GaleError) as ei:
+            gale.Context(**kw)
+        assert ei.value.status == gale.EINVAL
+
+
 def test_create_without_device_is_edevice():
     import torch
     if torch.cuda.is_available():

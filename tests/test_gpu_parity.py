@@ -277,37 +277,43 @@ def test_hybrid_path_small_budgets(lds):
 
 def test_refined_256_full_size_sampled():
     """The 256^3 lattice refined in Gaussian blobs (34M vertices, 151M
-    tetrahedra, 40,579 lognormal clusters of 64..8192 vertices) built in one
-    batched launch; a seeded sample of clusters plus the four largest compared
-    with the oracle; no block needs the exhaustive TT pairing."""
+    tetrahedra, 40,579 lognormal clusters of 64..8192 vertices) built the way
+    the benchmark times it: every cluster in one graph replay of the
+    persistent launches (workgroup shapes 1024/512/256 and the hybrid global
+    path on 65 % of the CUs, launched first).  A seeded sample of clusters,
+    the four largest and the first and last are read from that batch's device
+    blocks and compared with the oracle; no block needs the exhaustive TT
+    pairing and no cluster the all-global path."""
     gale = _gale()
     m = meshgen.config(3)
     _say("256^3 refined", m.nv, m.nt, m.nclusters)
     sizes = np.bincount(m.cluster, minlength=m.nclusters)
-    with gale.Context(form="batched") as ctx:
+    rng = np.random.default_rng(31)
+    sample = sorted(set(rng.choice(m.nclusters, 20, replace=False).tolist())
+                    | set(np.argsort(-sizes)[:4].tolist()) | {0, m.nclusters - 1})
+    with gale.Context(form="batched", launch_classes=6, global_cu_share=0.65) as ctx:
         ctx.load(m.tets, m.cluster, m.nclusters)
         _say("loaded")
-        tk = ctx.build(np.arange(m.nclusters, dtype=np.int32), 7, "batched")
+        g = ctx.graph_create(np.arange(m.nclusters, dtype=np.int32), 7)
+        tk = ctx.graph_launch(g)
         ctx.poll(tk)
         st = ctx.stats()
         _say("built", st["entries_built"], "global-path blocks", st["global_path_blocks"],
-             "exhaustive", st["tt_exhaustive_blocks"])
+             "hybrid", st["hybrid_path_blocks"], "exhaustive", st["tt_exhaustive_blocks"])
         assert st["tt_exhaustive_blocks"] == 0
-        ctx.release(tk)
-        rng = np.random.default_rng(31)
-        sample = sorted(set(rng.choice(m.nclusters, 20, replace=False).tolist())
-                        | set(np.argsort(-sizes)[:4].tolist()) | {0, m.nclusters - 1})
+        assert st["global_path_blocks"] > 0 and st["hybrid_path_blocks"] == st["global_path_blocks"]
         orc = oracle.Oracle.of(m)
         _say("oracle ready")
-        tk = ctx.submit(np.array(sample, np.int32), 7)
         bad = []
         for k in sample:
             for rel in REL:
-                got = ctx.block(tk, int(k), rel)
+                v = ctx.block_device(tk, int(k), rel)
+                got = (_d2h(v.row_ids, v.nrows), _d2h(v.offsets, v.nrows + 1), _d2h(v.entries, v.nnz))
                 exp = orc.block(int(k), rel)
-                if not all(np.array_equal(g, e) for g, e in zip(got, exp)):
+                if not all(np.array_equal(a, b) for a, b in zip(got, exp)):
                     bad.append((int(k), rel))
         ctx.release(tk)
+        ctx.graph_destroy(g)
     assert not bad, bad
 
 
@@ -371,6 +377,35 @@ def test_graph_replays_equal_oracle():
         assert ei.value.status == gale.ENOENT
 
 
+@pytest.mark.parametrize("share", [0.5, 0.8])
+def test_global_launch_on_a_share_of_the_cus(share):
+    """The global-path launch on a share of the CUs, launched before the
+    LDS-path classes (fewer workgroups than hybrid clusters, so each takes
+    several from its queue): every block equals the oracle's, built directly
+    and from a graph replay."""
+    gale = _gale()
+    m, orc = _refined36()
+    ids = np.arange(m.nclusters, dtype=np.int32)
+    with gale.Context(form="batched", launch_classes=6, global_cu_share=share) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        assert ctx.stats()["global_cu_share"] == share
+        compare_all(ctx, m, orc)
+        assert ctx.stats()["hybrid_path_blocks"] > 0
+        g = ctx.graph_create(ids, 7)
+        tk = ctx.graph_launch(g)
+        ctx.poll(tk)
+        bad = []
+        for k in range(m.nclusters):
+            for rel in REL:
+                v = ctx.block_device(tk, k, rel)
+                got = (_d2h(v.row_ids, v.nrows), _d2h(v.offsets, v.nrows + 1), _d2h(v.entries, v.nnz))
+                if not all(np.array_equal(a, b) for a, b in zip(got, orc.block(k, rel))):
+                    bad.append((k, rel))
+        ctx.release(tk)
+        ctx.graph_destroy(g)
+        assert not bad, bad[:5]
+
+
 def test_autotune_keeps_results():
     gale = _gale()
     m = meshgen.refined_mesh(36, 0.05, 3, 512, 1.0, seed=11)
@@ -378,8 +413,9 @@ def test_autotune_keeps_results():
     with gale.Context(form="batched") as ctx:
         ctx.load(m.tets, m.cluster, m.nclusters)
         chosen, ms = ctx.autotune(np.arange(m.nclusters, dtype=np.int32), 7, reps=2)
-        _say("autotune", chosen, ms)
+        _say("autotune", chosen, ms, "share", ctx.stats()["global_cu_share"])
         assert chosen in (0, 2, 4, 6) and all(v > 0 for v in ms.values())
+        assert ctx.stats()["global_cu_share"] in (1.0, 0.8, 0.65, 0.5)
         compare_all(ctx, m, orc)
 
 
