@@ -927,16 +927,26 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                     for (int d = G / 2; d >= 1; d >>= 1) c += __shfl_xor(c, d, G);
                     if (gl == 0) s_vc[par][grp] = c;
                     __syncthreads();
-                    // this round's offsets: base + counts of the groups before
-                    int x = 0;
-                    for (int j = gl; j < NG; j += G) x += (j < grp) ? s_vc[par][j] : 0;
-                    int round_total = 0;
-                    for (int j = gl; j < NG; j += G) round_total += s_vc[par][j];
+                    // this round's offsets: base + counts of the groups before.
+                    // Every wave scans the NG counts itself, one or two per lane.
+                    constexpr int E = NG > 64 ? 2 : 1;
+                    const int lane = tid & 63;
+                    const int a0 = lane * E < NG ? s_vc[par][lane * E] : 0;
+                    const int a1 = (E == 2 && lane * E + 1 < NG) ? s_vc[par][lane * E + 1] : 0;
+                    const int lsum = a0 + a1;
+                    int incl = lsum;
 #pragma unroll
-                    for (int d = G / 2; d >= 1; d >>= 1) {
-                        x += __shfl_xor(x, d, G);
-                        round_total += __shfl_xor(round_total, d, G);
+                    for (int d = 1; d < 64; d <<= 1) {
+                        const int y = __shfl_up(incl, d, 64);
+                        if (lane >= d) incl += y;
                     }
+                    const int src = grp / E;
+                    int x = __shfl(incl - lsum, src, 64);
+                    if (E == 2) {
+                        const int f = __shfl(a0, src, 64);
+                        if (grp & 1) x += f;
+                    }
+                    const int round_total = __shfl(incl, 63, 64);
                     const int o_row = base_off + x;
                     par ^= 1;
                     if (r < nV) {
