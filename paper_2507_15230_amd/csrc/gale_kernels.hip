@@ -873,10 +873,24 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                 // words each) and visits only the words marked in them
                 const int SW = (W + 31) / 32, SK = (SW + G - 1) / G;
                 const int sbeg = gl * SK, send = min(SW, sbeg + SK);
-                auto mark = [&](int v, int self) {
-                    if (v != self) {
-                        atomicOr(&wb[v >> 5], 1u << (v & 31));
-                        if (!in_regs) atomicOr(&sb[v >> 10], 1u << ((v >> 5) & 31));
+                auto mark = [&](int v) {
+                    atomicOr(&wb[v >> 5], 1u << (v & 31));
+                    if (!in_regs) atomicOr(&sb[v >> 10], 1u << ((v >> 5) & 31));
+                };
+                // the row vertex is one of each tetrahedron's four ascending
+                // ids: the other three by selects, then marked
+                auto mark_others = [&](int4 t, int self) {
+                    const bool sx = t.x == self, sy = t.y == self;
+                    mark(sx ? t.y : t.x);
+                    mark((sx || sy) ? t.z : t.y);
+                    mark(t.w == self ? t.z : t.w);
+                };
+                auto entry_tet = [&](int i) -> int4 {
+                    if constexpr (kH) {
+                        const ushort4 q = lv4[i];
+                        return make_int4(q.x, q.y, q.z, q.w);
+                    } else {
+                        return tet(lvt[i]);
                     }
                 };
                 int par = 0;
@@ -884,19 +898,15 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                     const int r = r0 + grp;
                     if (r < nV) {
                         const int self = rowl[r];
-                        for (int i = cnt[r] + gl; i < cnt[r + 1]; i += G) {
-                            int4 t;
-                            if constexpr (kH) {
-                                const ushort4 q = lv4[i];
-                                t = make_int4(q.x, q.y, q.z, q.w);
-                            } else {
-                                t = tet(lvt[i]);
-                            }
-                            mark(t.x, self);
-                            mark(t.y, self);
-                            mark(t.z, self);
-                            mark(t.w, self);
+                        const int e1 = cnt[r + 1];
+                        int i = cnt[r] + gl;
+                        // two entries per step, their reads overlapped
+                        for (; i + G < e1; i += 2 * G) {
+                            const int4 t0 = entry_tet(i), t1 = entry_tet(i + G);
+                            mark_others(t0, self);
+                            mark_others(t1, self);
                         }
+                        if (i < e1) mark_others(entry_tet(i), self);
                     }
                     wave_fence();
                     // this lane's run of words: into registers (and cleared), counted
