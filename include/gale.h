@@ -82,9 +82,10 @@ typedef struct {
                                      placing its most used ones in LDS when they fit (used by tests). */
     void    *hip_stream;          /* borrowed hipStream_t for DIRECT mode work, or NULL for a library-owned stream.
                                      Must outlive the context. */
-    double   global_cu_share;     /* BATCHED form: share of the CUs (0 < s <= 1) the global-path launch takes when
-                                     LDS-path launch classes run beside it (it is then launched first); 0 = 1.
-                                     gale_autotune may change it. */
+    double   global_cu_share;     /* DIRECT mode, BATCHED form: share of the CUs (0 < s <= 1) the global-path
+                                     launch takes when LDS-path launch classes run beside it (it is then launched
+                                     first); 0 = 1.  gale_autotune may change it.  SERVE mode runs a batch's
+                                     launches one after another and always gives the global launch every CU. */
 } gale_config;
 
 /* A read-only view of one CSR block.  For gale_block the pointers are host

@@ -291,10 +291,13 @@ gale_status stage_items(gale_ctx *ctx, int form, const std::vector<WorkItem> &it
     n_glob = (int)glob.size();
     order.insert(order.end(), glob.begin(), glob.end());
     // workgroups of the global launch: a global-path workgroup takes a whole
-    // CU; when LDS-path classes run beside it, it gets the context's share of
-    // the CUs (gale_autotune sets it), alone every CU
+    // CU; when LDS-path classes run beside it (DIRECT mode forks the launches
+    // onto streams of their own), it gets the context's share of the CUs
+    // (gale_autotune sets it); alone or one launch after another, every CU
     int glob_grid = ctx->grid_glob;
-    if (n_glob > 0 && n_glob < n) glob_grid = std::max(1, (int)(ctx->glob_share * ctx->grid_glob + 0.5));
+    const bool side_by_side = ctx->cfg.mode == GALE_MODE_DIRECT && !ctx->aux.empty();
+    if (n_glob > 0 && n_glob < n && side_by_side)
+        glob_grid = std::max(1, (int)(ctx->glob_share * ctx->grid_glob + 0.5));
     ncls.push_back(glob_grid);
     wsb = workspace_bytes(ctx, glob, nullptr);
     ctx->n_global_blocks += n_glob;
