@@ -36,7 +36,7 @@ import numpy as np
 __all__ = [
     "Mesh", "kuhn_grid", "morton_keys", "clusters_fixed", "clusters_lognormal",
     "refine", "grid_mesh", "refined_mesh", "config", "CONFIGS",
-    "cube", "fig1_toy", "fig4_example", "single_tet", "random_small", "fans", "nonmanifold", "gauss_field",
+    "cube", "fig1_toy", "fig4_example", "single_tet", "random_small", "fans", "nonmanifold", "loose_tets", "gauss_field",
 ]
 
 
@@ -437,6 +437,28 @@ def nonmanifold(n: int = 5, fins: int = 6, dups: int = 3, nclusters: int = 3, se
     tets, cluster, _, _ = _permute(rng, tets, cluster, None, None)
     return Mesh(tets=np.ascontiguousarray(tets), cluster=cluster, nclusters=nclusters,
                 meta={"kind": "nonmanifold", "n": n, "fins": fins, "dups": dups, "seed": seed})
+
+
+def loose_tets(singles: int = 800, pairs: int = 100, seed: int = 0) -> Mesh:
+    """Tetrahedra sharing almost no faces: `singles` tetrahedra on vertices of
+    their own and `pairs` pairs sharing one triangle, all in one cluster
+    (3.9 distinct faces per tetrahedron for the defaults, more than a closed
+    region's 2 plus boundary).  Random vertex and tetrahedron ids.  Draw order:
+    vperm, tperm."""
+    rng = np.random.default_rng(seed)
+    tets, v = [], 0
+    for _ in range(singles):
+        tets.append([v, v + 1, v + 2, v + 3])
+        v += 4
+    for _ in range(pairs):
+        tets.append([v, v + 1, v + 2, v + 3])
+        tets.append([v, v + 1, v + 2, v + 4])
+        v += 5
+    tets = np.array(tets, dtype=np.int32)
+    cluster = np.zeros(v, dtype=np.int32)
+    tets, cluster, _, _ = _permute(rng, tets, cluster, None, None)
+    return Mesh(tets=np.ascontiguousarray(tets), cluster=cluster, nclusters=1,
+                meta={"kind": "loose_tets", "singles": singles, "pairs": pairs, "seed": seed})
 
 
 def random_small(seed: int, n: int = 4, nclusters: int = 5, drop: float = 0.3,

@@ -463,3 +463,27 @@ def test_nonmanifold_faces(path):
             assert st["hybrid_path_blocks"] > 0
         if path == "global":
             assert st["global_path_blocks"] > 0 and st["hybrid_path_blocks"] == 0
+
+
+@pytest.mark.parametrize("path,lds", [("lds", 23964), ("hybrid", 15664)])
+def test_face_table_overflow_doubles_passes(path, lds):
+    """Loose tetrahedra (3,900 distinct faces for 1,000 TT rows) overflow the
+    face table sized by the estimate of 2.5 faces per row at load 0.7: with
+    these budgets the LDS plan starts with one pass over 3,750 cells and the
+    hybrid plan with two over 1,900, so a pass fills its table and the kernel
+    starts again with twice the passes.  The blocks still equal the oracle's
+    and no cluster needs exhaustive pairing."""
+    gale = _gale()
+    m = meshgen.loose_tets()
+    orc = oracle.Oracle.of(m)
+    _say("face table overflow", path, lds)
+    with gale.Context(form="batched", lds_bytes=lds) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        compare_all(ctx, m, orc, mask=4)
+        st = ctx.stats()
+        assert st["tt_exhaustive_blocks"] == 0
+        if path == "hybrid":
+            assert st["hybrid_path_blocks"] > 0
+        else:
+            assert st["global_path_blocks"] == 0
+        compare_all(ctx, m, orc)
