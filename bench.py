@@ -246,8 +246,9 @@ def main():
         summarize_profile(*args.summarize_profile)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (clusters are independent; "
-              "see the sharding note in DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (clusters are independent, so "
+              "Morton ranges of cluster ids would go to separate GPUs with no per-request collective). "
+              "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
