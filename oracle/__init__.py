@@ -59,6 +59,15 @@ def _load():
     lib.oracle_owner.restype = C.c_int32
     lib.oracle_vt_degree.argtypes = [C.c_void_p, C.c_int32]
     lib.oracle_vt_degree.restype = C.c_int64
+    lib.oracle_buf_new.argtypes = []
+    lib.oracle_buf_new.restype = C.c_void_p
+    lib.oracle_buf_free.argtypes = [C.c_void_p]
+    lib.oracle_buf_free.restype = None
+    lib.oracle_block_into.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int64)]
+    lib.oracle_block_into.restype = C.c_int
+    lib.oracle_buf_copy.argtypes = [C.c_void_p, i32p, i32p, i32p]
+    lib.oracle_buf_copy.restype = None
     _lib = lib
     return lib
 
@@ -122,6 +131,45 @@ class Oracle:
         self._lib.oracle_block_copy(self._h, rows.ctypes.data_as(i32p), offs.ctypes.data_as(i32p),
                                     ents.ctypes.data_as(i32p))
         return rows, offs, ents
+
+    def blocks(self, pairs, threads: int | None = None):
+        """The blocks of many (cluster, relation) pairs, built by several
+        threads sharing this context (each with its own buffer); returns a
+        list of (row_ids, offsets, entries) in the order of ``pairs``.  The
+        planted-mistake switch must be off."""
+        import threading
+        from concurrent.futures import ThreadPoolExecutor
+        pairs = list(pairs)
+        threads = threads or min(16, os.cpu_count() or 1)
+        local = threading.local()
+        bufs = []
+        lock = threading.Lock()
+        i32p = C.POINTER(C.c_int32)
+
+        def one(kr):
+            b = getattr(local, "b", None)
+            if b is None:
+                b = local.b = self._lib.oracle_buf_new()
+                with lock:
+                    bufs.append(b)
+            nr = C.c_int64()
+            nz = C.c_int64()
+            st = self._lib.oracle_block_into(self._h, b, int(kr[0]), int(kr[1]), C.byref(nr), C.byref(nz))
+            if st != 0:
+                raise ValueError("oracle_block_into(%d, %d) failed with status %d" % (kr[0], kr[1], st))
+            rows = np.empty(nr.value, dtype=np.int32)
+            offs = np.empty(nr.value + 1, dtype=np.int32)
+            ents = np.empty(nz.value, dtype=np.int32)
+            self._lib.oracle_buf_copy(b, rows.ctypes.data_as(i32p), offs.ctypes.data_as(i32p),
+                                      ents.ctypes.data_as(i32p))
+            return rows, offs, ents
+
+        try:
+            with ThreadPoolExecutor(max_workers=threads) as ex:
+                return list(ex.map(one, pairs))
+        finally:
+            for b in bufs:
+                self._lib.oracle_buf_free(b)
 
     def owner(self, t: int) -> int:
         return int(self._lib.oracle_owner(self._h, int(t)))

@@ -48,6 +48,15 @@
 #define REL_VV 2
 #define REL_TT 4
 
+/* One block's arrays (rows, offsets, entries) and their capacities.  A
+ * context is read-only while blocks are built, so threads that each own a
+ * buffer may build blocks of one context at the same time. */
+typedef struct {
+    int64_t nrows, nnz;
+    int32_t *rows, *off, *ent;
+    int64_t cap_rows, cap_ent;
+} oracle_buf;
+
 typedef struct {
     int32_t nv;
     int64_t nt;
@@ -63,10 +72,7 @@ typedef struct {
     int32_t *trows;     /* nt: tetrahedra grouped by owner, ascending id */
     int mutation;
     int owner_mut;      /* mutation the owner table was built under */
-    /* last block built */
-    int64_t b_nrows, b_nnz;
-    int32_t *b_rows, *b_off, *b_ent;
-    int64_t b_cap_rows, b_cap_ent;
+    oracle_buf b;       /* the block last built by oracle_block */
 } oracle_ctx;
 
 static int cmp_i32(const void *a, const void *b) {
@@ -88,7 +94,7 @@ void oracle_destroy(oracle_ctx *c) {
     if (!c) return;
     free(c->tv); free(c->cl); free(c->vt_off); free(c->vt); free(c->owner);
     free(c->vrow_off); free(c->vrows); free(c->trow_off); free(c->trows);
-    free(c->b_rows); free(c->b_off); free(c->b_ent);
+    free(c->b.rows); free(c->b.off); free(c->b.ent);
     free(c);
 }
 
@@ -201,19 +207,19 @@ static void refresh_rows(oracle_ctx *c) {
     c->owner_mut = c->mutation;
 }
 
-static int reserve(oracle_ctx *c, int64_t rows, int64_t ent) {
-    if (rows + 1 > c->b_cap_rows) {
-        free(c->b_rows); free(c->b_off);
-        c->b_cap_rows = rows + 1;
-        c->b_rows = (int32_t *)malloc(sizeof(int32_t) * (size_t)c->b_cap_rows);
-        c->b_off = (int32_t *)malloc(sizeof(int32_t) * (size_t)(c->b_cap_rows + 1));
-        if (!c->b_rows || !c->b_off) return ORC_ENOMEM;
+static int reserve(oracle_buf *b, int64_t rows, int64_t ent) {
+    if (rows + 1 > b->cap_rows) {
+        free(b->rows); free(b->off);
+        b->cap_rows = rows + 1;
+        b->rows = (int32_t *)malloc(sizeof(int32_t) * (size_t)b->cap_rows);
+        b->off = (int32_t *)malloc(sizeof(int32_t) * (size_t)(b->cap_rows + 1));
+        if (!b->rows || !b->off) return ORC_ENOMEM;
     }
-    if (ent > c->b_cap_ent) {
-        free(c->b_ent);
-        c->b_cap_ent = ent + ent / 2 + 16;
-        c->b_ent = (int32_t *)malloc(sizeof(int32_t) * (size_t)c->b_cap_ent);
-        if (!c->b_ent) return ORC_ENOMEM;
+    if (ent > b->cap_ent) {
+        free(b->ent);
+        b->cap_ent = ent + ent / 2 + 16;
+        b->ent = (int32_t *)malloc(sizeof(int32_t) * (size_t)b->cap_ent);
+        if (!b->ent) return ORC_ENOMEM;
     }
     return ORC_OK;
 }
@@ -234,12 +240,12 @@ static int64_t intersect3(const int32_t *a, int64_t na, const int32_t *b, int64_
     return w;
 }
 
-/* O2-O4: build the block (cluster k, one relation) into the context's
- * buffers.  Returns status; *nrows / *nnz receive the sizes. */
-int oracle_block(oracle_ctx *c, int32_t k, int32_t rel, int64_t *nrows, int64_t *nnz) {
+/* O2-O4: build the block (cluster k, one relation) into buffer b.  Returns
+ * status; *nrows / *nnz receive the sizes.  Reads the context only. */
+int oracle_block_into(const oracle_ctx *c, oracle_buf *b, int32_t k, int32_t rel, int64_t *nrows, int64_t *nnz) {
     if (k < 0 || k >= c->ncl) return ORC_EINVAL;
     if (rel != REL_VT && rel != REL_VV && rel != REL_TT) return ORC_EINVAL;
-    if ((c->mutation == 3) != (c->owner_mut == 3)) refresh_rows(c);
+    if ((c->mutation == 3) != (c->owner_mut == 3)) return ORC_EINVAL;  /* owner table of another mutation */
     if (rel == REL_VT || rel == REL_VV) {
         const int32_t *rows = c->vrows + c->vrow_off[k];
         int64_t n = c->vrow_off[k + 1] - c->vrow_off[k];
@@ -249,18 +255,18 @@ int oracle_block(oracle_ctx *c, int32_t k, int32_t rel, int64_t *nrows, int64_t 
             int64_t deg = c->vt_off[v + 1] - c->vt_off[v];
             cap += rel == REL_VT ? deg : 4 * deg;
         }
-        if (reserve(c, n, cap + 1)) return ORC_ENOMEM;
+        if (reserve(b, n, cap + 1)) return ORC_ENOMEM;
         int64_t w = 0;
-        c->b_off[0] = 0;
+        b->off[0] = 0;
         for (int64_t r = 0; r < n; ++r) {
             int32_t v = rows[c->mutation == 7 ? n - 1 - r : r];
-            c->b_rows[r] = v;
+            b->rows[r] = v;
             const int32_t *lst = c->vt + c->vt_off[v];
             int64_t deg = c->vt_off[v + 1] - c->vt_off[v];
             if (rel == REL_VT) {
                 if (c->mutation == 8 && deg > 0) deg -= 1;
                 for (int64_t i = 0; i < deg; ++i)
-                    c->b_ent[w + i] = lst[c->mutation == 4 ? deg - 1 - i : i];
+                    b->ent[w + i] = lst[c->mutation == 4 ? deg - 1 - i : i];
                 w += deg;
             } else {
                 int64_t s = w;
@@ -268,11 +274,11 @@ int oracle_block(oracle_ctx *c, int32_t k, int32_t rel, int64_t *nrows, int64_t 
                 for (int64_t i = 0; i < use; ++i) {
                     const int32_t *q = c->tv + 4 * (int64_t)lst[i];
                     for (int j = 0; j < 4; ++j)
-                        if (q[j] != v || c->mutation == 1) c->b_ent[w++] = q[j];
+                        if (q[j] != v || c->mutation == 1) b->ent[w++] = q[j];
                 }
-                w = s + sort_unique(c->b_ent + s, w - s);
+                w = s + sort_unique(b->ent + s, w - s);
             }
-            c->b_off[r + 1] = (int32_t)w;
+            b->off[r + 1] = (int32_t)w;
         }
         *nrows = n;
         *nnz = w;
@@ -291,12 +297,12 @@ int oracle_block(oracle_ctx *c, int32_t k, int32_t rel, int64_t *nrows, int64_t 
             }
             cap += 4 * mx;
         }
-        if (reserve(c, n, cap + 1)) return ORC_ENOMEM;
+        if (reserve(b, n, cap + 1)) return ORC_ENOMEM;
         int64_t w = 0;
-        c->b_off[0] = 0;
+        b->off[0] = 0;
         for (int64_t r = 0; r < n; ++r) {
             int32_t t = rows[r];
-            c->b_rows[r] = t;
+            b->rows[r] = t;
             const int32_t *q = c->tv + 4 * (int64_t)t;
             int64_t s = w;
             int nfaces = c->mutation == 9 ? 3 : 4;
@@ -313,30 +319,50 @@ int oracle_block(oracle_ctx *c, int32_t k, int32_t rel, int64_t *nrows, int64_t 
                 int64_t nc = c->vt_off[f[2] + 1] - c->vt_off[f[2]];
                 int64_t got;
                 if (c->mutation == 5) /* wrong: adjacency through an edge */
-                    got = intersect3(la, na, lb, nb, lb, nb, c->b_ent + w);
+                    got = intersect3(la, na, lb, nb, lb, nb, b->ent + w);
                 else
-                    got = intersect3(la, na, lb, nb, lc, nc, c->b_ent + w);
+                    got = intersect3(la, na, lb, nb, lc, nc, b->ent + w);
                 int64_t keep = 0;
                 for (int64_t i = 0; i < got; ++i)
-                    if (c->b_ent[w + i] != t || c->mutation == 2) c->b_ent[w + keep++] = c->b_ent[w + i];
+                    if (b->ent[w + i] != t || c->mutation == 2) b->ent[w + keep++] = b->ent[w + i];
                 w += keep;
             }
-            w = s + sort_unique(c->b_ent + s, w - s);
-            c->b_off[r + 1] = (int32_t)w;
+            w = s + sort_unique(b->ent + s, w - s);
+            b->off[r + 1] = (int32_t)w;
         }
         *nrows = n;
         *nnz = w;
     }
-    c->b_nrows = *nrows;
-    c->b_nnz = *nnz;
+    b->nrows = *nrows;
+    b->nnz = *nnz;
     return ORC_OK;
 }
 
-/* copy the last block out: rows[nrows], offsets[nrows+1], entries[nnz] */
+/* The same into the context's own buffer (one caller at a time); switches
+ * the owner table when the owner mutation was turned on or off. */
+int oracle_block(oracle_ctx *c, int32_t k, int32_t rel, int64_t *nrows, int64_t *nnz) {
+    if ((c->mutation == 3) != (c->owner_mut == 3)) refresh_rows(c);
+    return oracle_block_into(c, &c->b, k, rel, nrows, nnz);
+}
+
+/* copy a buffer's block out: rows[nrows], offsets[nrows+1], entries[nnz] */
+void oracle_buf_copy(const oracle_buf *b, int32_t *rows, int32_t *offsets, int32_t *entries) {
+    if (b->nrows) memcpy(rows, b->rows, sizeof(int32_t) * (size_t)b->nrows);
+    memcpy(offsets, b->off, sizeof(int32_t) * (size_t)(b->nrows + 1));
+    if (b->nnz) memcpy(entries, b->ent, sizeof(int32_t) * (size_t)b->nnz);
+}
+
+/* copy the last block of oracle_block out */
 void oracle_block_copy(const oracle_ctx *c, int32_t *rows, int32_t *offsets, int32_t *entries) {
-    if (c->b_nrows) memcpy(rows, c->b_rows, sizeof(int32_t) * (size_t)c->b_nrows);
-    memcpy(offsets, c->b_off, sizeof(int32_t) * (size_t)(c->b_nrows + 1));
-    if (c->b_nnz) memcpy(entries, c->b_ent, sizeof(int32_t) * (size_t)c->b_nnz);
+    oracle_buf_copy(&c->b, rows, offsets, entries);
+}
+
+oracle_buf *oracle_buf_new(void) { return (oracle_buf *)calloc(1, sizeof(oracle_buf)); }
+
+void oracle_buf_free(oracle_buf *b) {
+    if (!b) return;
+    free(b->rows); free(b->off); free(b->ent);
+    free(b);
 }
 
 /* accessors used by the tests */
