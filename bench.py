@@ -1,19 +1,24 @@
 """Benchmark: VT/VV/TT relation entries per second on one MI355X.
 
-One step = every cluster of the 128^3 Kuhn lattice (2,097,152 vertices,
-12,290,298 tetrahedra, 2048 Morton clusters of 1024 vertices) built into HBM
-with all three relations in one batched persistent launch.  The mesh streams
-are resident in HBM before timing starts; copies to the host are not part of a
-step.  Prints one JSON line.
+One step = every cluster of the workload's mesh built into HBM with all
+three relations, as one hipGraph replay of the batched persistent launches
+(the launch shapes read from the tune table the project's autotuner wrote, or
+tuned on the spot).  The default workload is the 256^3 lattice refined in
+Gaussian blobs (34,050,862 vertices, 151,309,188 tetrahedra, 40,579 lognormal
+Morton clusters).  The mesh streams are resident in HBM before timing starts;
+copies to the host are not part of a step.  Around the timed steps the run
+also measures: the same build as one launch per (cluster, relation) ("plain"),
+the serving loop with 40 consumer threads under an HBM cache budget against
+synchronous plain per-cluster requests, and the CPU oracle on a bounded sample
+(one thread, then every allowed host thread).  Prints one JSON line.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config C]
 """
 from __future__ import annotations
 
 import argparse
 import csv
 import glob
-import hashlib
 import json
 import os
 import sys
@@ -26,6 +31,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TUNE_TABLE = os.path.join(ROOT, "paper_2507_15230_amd", "tune_mi355x.json")
 WORKLOADS = {
     1: "32^3 Kuhn lattice (32,768 vertices, 178,746 tetrahedra), seed-permuted, 64 Morton clusters of 512 "
        "vertices; VT+VV+TT for every cluster in one batched launch",
@@ -33,189 +39,234 @@ WORKLOADS = {
        "1024 vertices; VT+VV+TT for every cluster in one batched launch",
     3: "256^3 Kuhn lattice refined by 3 rounds of centroid splits of 5% of the tetrahedra in 8 Gaussian blobs "
        "(34,050,862 vertices, 151,309,188 tetrahedra), lognormal Morton clusters (median 512, sigma 1, 64..8192; "
-       "40,579 clusters); VT+VV+TT for every cluster in one batched launch, autotuned launch classes",
-    4: "the 256^3 refined mesh with a 16-Gaussian scalar field; batched build as for the refined mesh, then the "
-       "serving workload (40 consumer threads, 4 GB HBM relation cache)",
+       "40,579 clusters); VT+VV+TT for every cluster in one hipGraph-captured batched submit, tuned launch shapes",
+    4: "the 256^3 refined mesh with a 16-Gaussian scalar field (config 3's mesh, own permutation); batched "
+       "build as for config 3, then the serving workload (40 consumer threads, 4 GB HBM relation cache)",
+    5: "384^3 Kuhn lattice refined by 2 rounds of centroid splits of 3% of the tetrahedra in 8 Gaussian blobs "
+       "(77,758,730 vertices, 400,498,200 tetrahedra), lognormal Morton clusters (median 1024, sigma 1.2, "
+       "64..8192; 42,669 clusters); VT+VV+TT for every cluster in one hipGraph-captured batched submit, then "
+       "serving with 40 consumers under 8 / 32 / 128 GB cache budgets",
 }
-KERNEL_SOURCES = ["paper_2507_15230_amd/csrc/gale_kernels.hip", "paper_2507_15230_amd/csrc/gale_layout.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "persistent_kernel_traffic_128cubed.json")
 COPY_BYTES = 256 << 20
-
-
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
-
-
-def measured_traffic():
-    """HBM bytes per persistent launch from the committed FETCH_SIZE/WRITE_SIZE
-    summary, if it was taken on the current kernel source; else None."""
-    try:
-        with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if t.get("kernel_source_sha256") != kernel_source_hash():
-        return None
-    return t.get("traffic_bytes_per_launch")
-
-
-def summarize_profile(kt_dir, fetch_dir, write_dir, out_md, out_json, cmd_kt, cmd_fetch, cmd_write):
-    """Turn rocprofv3 CSV output into the committed text summary and the
-    traffic record bench.py reads back."""
-    stats = glob.glob(os.path.join(kt_dir, "**", "*kernel_stats.csv"), recursive=True)
-    lines = ["# rocprofv3 kernel statistics: 128^3 lattice, 2048 clusters, VT+VV+TT batched", "",
-             "Command: `%s`" % cmd_kt, "", "| kernel | calls | total ms | avg us | min us | max us |",
-             "|---|---|---|---|---|---|"]
-    avg_persistent = None
-    for fn in stats:
-        for r in csv.DictReader(open(fn)):
-            name = r.get("Name") or r.get("KernelName") or ""
-            calls = int(float(r.get("Calls", 0)))
-            tot = float(r.get("TotalDurationNs", 0)) / 1e6
-            avg = float(r.get("AverageNs", 0)) / 1e3
-            mn = float(r.get("MinNs", 0)) / 1e3
-            mx = float(r.get("MaxNs", 0)) / 1e3
-            lines.append("| %s | %d | %.3f | %.1f | %.1f | %.1f |" % (name[:90], calls, tot, avg, mn, mx))
-            if "gale_persistent_kernel" in name and ", true>" in name:
-                avg_persistent = avg
-    traffic = {}
-    for tag, d in (("fetch", fetch_dir), ("write", write_dir)):
-        for fn in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
-            per = {}
-            for r in csv.DictReader(open(fn)):
-                per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
-            traffic[tag] = per
-    copy_name = None
-    res = {"kernel_source_sha256": kernel_source_hash(), "commands": [cmd_kt, cmd_fetch, cmd_write]}
-    if "fetch" in traffic and "write" in traffic:
-        def pick(per, pred):
-            for k, v in per.items():
-                if pred(k):
-                    return k, sum(v) / len(v)
-            return None, None
-        copy_name, copy_fetch = pick(traffic["fetch"], lambda k: "neg" in k.lower())
-        _, copy_write = pick(traffic["write"], lambda k: k == copy_name)
-        kname, k_fetch = pick(traffic["fetch"], lambda k: "gale_persistent_kernel" in k and ", true>" in k)
-        _, k_write = pick(traffic["write"], lambda k: k == kname)
-        if copy_fetch and copy_write and k_fetch is not None and k_write is not None:
-            f_fac = COPY_BYTES / (copy_fetch * 1024.0)
-            w_fac = COPY_BYTES / (copy_write * 1024.0)
-            tb = k_fetch * 1024.0 * f_fac + k_write * 1024.0 * w_fac
-            res.update({"copy_kernel": copy_name, "copy_bytes": COPY_BYTES, "copy_fetch_kib": copy_fetch,
-                        "copy_write_kib": copy_write, "fetch_factor": f_fac, "write_factor": w_fac,
-                        "kernel": kname, "fetch_kib_per_dispatch": k_fetch, "write_kib_per_dispatch": k_write,
-                        "traffic_bytes_per_launch": tb, "avg_kernel_us": avg_persistent})
-            lines += ["", "## HBM traffic (rocprofv3 --pmc, per dispatch)", "",
-                      "Commands: `%s` and `%s`" % (cmd_fetch, cmd_write), "",
-                      "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB |", "|---|---|---|",
-                      "| %s | %.0f | %.0f |" % (kname[:90], k_fetch, k_write),
-                      "| %s (%d MiB copy) | %.0f | %.0f |" % (copy_name[:60], COPY_BYTES >> 20, copy_fetch, copy_write),
-                      "", "Scale factors from the copy (known bytes / counter): fetch %.3f, write %.3f." % (f_fac, w_fac),
-                      "Traffic per persistent launch: %.1f MB." % (tb / 1e6)]
-    with open(out_md, "w") as f:
-        f.write("\n".join(lines) + "\n")
-    with open(out_json, "w") as f:
-        json.dump(res, f, indent=1)
-    print("wrote", out_md, out_json)
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def output_bytes(entries: int, nv: int, nt: int, ncl: int) -> int:
-    """Bytes a step must write: entries, offsets (VT, VV per vertex row + 1 per
-    cluster, TT per tetrahedron row + 1 per cluster), row ids (vertex rows once,
-    tetrahedron rows) and an 8-word header per block."""
+def host_info() -> dict:
+    """CPU model, logical CPUs, the CPUs this process may use, and RAM."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    ram = 0
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                ram = int(line.split()[1]) * 1024
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "allowed_cpus": len(os.sched_getaffinity(0)),
+            "ram_bytes": ram}
+
+
+def alg_bytes(ctx, ncl: int, entries: int) -> tuple[int, dict]:
+    """Algorithmic bytes of one step: every cluster's star and halo
+    tetrahedra read once as four int32 vertex ids and an int32 tetrahedron id
+    (20 B each), every entry written (4 B), the offsets (VT and VV per vertex
+    row + 1, TT per tetrahedron row + 1) and the row ids (vertex rows once,
+    tetrahedron rows)."""
+    ns = nh = nv = nt = 0
+    for k in range(ncl):
+        i = ctx.cluster_info(k)
+        ns += i["ns"]
+        nh += i["nh"]
+        nv += i["nV"]
+        nt += i["nT"]
+    b = 20 * (ns + nh) + 4 * entries + 4 * (2 * nv + nt + 3 * ncl) + 4 * (nv + nt)
+    return b, {"star_tets": ns, "halo_tets": nh, "vertex_rows": nv, "tet_rows": nt}
+
+
+def stream_bytes(mesh_bytes: int, entries: int, nv: int, nt: int, ncl: int) -> int:
+    """Bytes as this library stores them: the compressed per-cluster streams
+    (4 x uint16 local ids per tetrahedron where a cluster's table allows, the
+    tetrahedron ids, the local vertex tables) read once, plus every output word
+    (entries, offsets, row ids, an 8-word header per block)."""
     words = entries + (2 * nv + 2 * ncl) + (nt + ncl) + nv + nt + 8 * ncl
-    return 4 * words
+    return mesh_bytes + 4 * words
 
 
-def cpu_baseline(mesh, budget_s: float = 15.0):
-    """The oracle as it stands, single-threaded, on the first clusters of the
-    same mesh until about budget_s seconds of block building."""
+def cpu_baseline(mesh, budget_s: float = 12.0, seed: int = 0):
+    """The oracle as it stands on a seeded random sample of the same mesh's
+    clusters: first on one thread until about budget_s seconds of block
+    building, then the same clusters on every allowed host thread (at most 16,
+    the box's share), cluster-parallel."""
     import oracle
     t0 = time.perf_counter()
     orc = oracle.Oracle.of(mesh)
     t_setup = time.perf_counter() - t0
+    order = np.random.default_rng(seed).permutation(mesh.nclusters)
     entries = 0
-    nclus = 0
+    done = []
     t1 = time.perf_counter()
-    for k in range(mesh.nclusters):
+    for k in order:
         for rel in (1, 2, 4):
-            _, _, e = orc.block(k, rel)
+            _, _, e = orc.block(int(k), rel)
             entries += len(e)
-        nclus += 1
+        done.append(int(k))
         if time.perf_counter() - t1 > budget_s:
             break
-    dt = time.perf_counter() - t1
+    dt1 = time.perf_counter() - t1
+    threads = min(16, len(os.sched_getaffinity(0)))
+    pairs = [(k, rel) for k in done for rel in (1, 2, 4)]
+    t2 = time.perf_counter()
+    res = orc.blocks(pairs, threads=threads)
+    dtn = time.perf_counter() - t2
+    assert sum(len(r[2]) for r in res) == entries
+    sample = ("seeded random sample of %d of %d clusters (VT+VV+TT blocks, %d entries); global VT and owner setup "
+              "%.1f s excluded" % (len(done), mesh.nclusters, entries, t_setup))
     return {
-        "value": entries / dt, "unit": "entries/s", "cores": 1, "kind": "oracle",
-        "sample": "first %d of %d clusters, VT+VV+TT blocks, %.1f s of block building; "
-                  "global VT/owner setup %.2f s excluded" % (nclus, mesh.nclusters, dt, t_setup),
+        "value": entries / dtn, "unit": "entries/s", "cores": threads, "kind": "oracle",
+        "sample": sample + "; %d threads cluster-parallel, %.2f s" % (threads, dtn),
+        "one_thread": {"value": entries / dt1, "unit": "entries/s", "cores": 1, "seconds": dt1},
+        "host": host_info(),
     }
 
 
-def serving_leg(mesh, args, pass_bytes: int):
+def serving_leg(mesh, budget: int, consumers: int, ncur: int, front_end: str = "single", plain: bool = True,
+                prefetch: int = 0):
     """Consumer threads (native, in the library) classify critical points
-    cluster by cluster (Morton order, Zipf(1.1) re-access), first through the
-    serving loop (continuous batching, HBM cache under a budget), then through
-    synchronous plain per-cluster launches with no cache; per-access latency
-    (submit -> ready) percentiles."""
+    cluster by cluster (Morton order, Zipf(1.1) re-access) through the serving
+    loop (continuous batching, HBM cache under `budget`); then, when `plain`,
+    the same consumers with synchronous plain per-cluster launches and no
+    cache.  Per-access latency (submit -> ready) percentiles and the paper's
+    waiting-time stages."""
     import meshgen
     from paper_2507_15230_amd import gale
     if mesh.scalar is not None:
         field = mesh.scalar
     else:
-        n = int(round(mesh.nv ** (1.0 / 3.0)))
+        n = int(round(mesh.meta.get("n", round(mesh.nv ** (1.0 / 3.0)))))
         field = meshgen.gauss_field(mesh.coords.astype(np.float64), n, np.random.default_rng(1))
-    if args.serving_budget_mb:
-        budget = args.serving_budget_mb << 20
-    elif args.config == 4:
-        budget = 4 << 30
-    else:
-        budget = pass_bytes // 2
-    ncur = args.serving_clusters if args.serving_clusters >= 0 else (mesh.nclusters if args.config <= 2 else 4096)
     order = np.arange(min(ncur, mesh.nclusters), dtype=np.int32)  # cluster ids are in Morton order
-    log("serving leg: %d consumers, budget %.0f MB" % (args.consumers, budget / 1e6))
-    ctx = gale.Context(device=0, mode="serve", cache_budget_bytes=budget, max_inflight=4,
-                       block_threads=args.block_threads)
+    log("serving: %d consumers, budget %.1f GB, front end %s, prefetch %d, %d clusters"
+        % (consumers, budget / 1e9, front_end, prefetch, order.shape[0]))
+    ctx = gale.Context(device=0, mode="serve", cache_budget_bytes=budget, max_inflight=4, front_end=front_end,
+                       prefetch_depth=prefetch)
     ctx.load(mesh.tets, mesh.cluster, mesh.nclusters)
-    res = gale.consumer_run(ctx, mesh.tets, field, order, threads=args.consumers)
+    res = gale.consumer_run(ctx, mesh.tets, field, order, threads=consumers)
     st = ctx.stats()
     ctx.close()
+    w = res["wall_s"]
     out = {
-        "workload": "the benchmark mesh with its 16-Gaussian scalar field; %d native consumer threads, Morton "
-                    "cursor, truncated Zipf(1.1) re-access, VT+VV+TT per access, critical points from VT and VV"
-                    % args.consumers,
-        "consumers": args.consumers, "cache_budget_bytes": int(budget), "max_inflight": 4,
-        "cursor_clusters": int(order.shape[0]),
-        "accesses": res["accesses"], "reaccesses": res["reaccesses"], "wall_s": res["wall_s"],
-        "accesses_per_s": res["accesses"] / res["wall_s"],
+        "consumers": consumers, "cache_budget_bytes": int(budget), "front_end": front_end,
+        "prefetch_depth": prefetch, "max_inflight": 4, "cursor_clusters": int(order.shape[0]),
+        "accesses": res["accesses"], "reaccesses": res["reaccesses"], "wall_s": w,
+        "accesses_per_s": res["accesses"] / w,
         "p50_us": res["lat_p50_us"], "p99_us": res["lat_p99_us"], "mean_us": res["lat_mean_us"],
         "max_us": res["lat_max_us"],
         "cache_hits": st["cache_hits"], "cache_misses": st["cache_misses"], "evictions": st["evictions"],
+        "prefetch": {k: st[k] for k in ("prefetch_built", "prefetch_hits", "prefetch_evicted", "demand_evictions")},
         "batches": st["batches"], "mean_batch_clusters": st["mean_batch_clusters"],
-        "entries_built_per_s": st["entries_built"] / res["wall_s"],
-        "entries_delivered_per_s": st["entries_delivered"] / res["wall_s"],
-        "stage_us": {"queue": st["stage_queue_us"], "build": st["stage_build_us"], "copy": st["stage_copy_us"]},
+        "queue_depth_mean": st["queue_depth_mean"], "queue_depth_max": st["queue_depth_max"],
+        "entries_built_per_s": st["entries_built"] / w, "entries_delivered_per_s": st["entries_delivered"] / w,
+        "stages_mean_us": {"push": st["stage_push_us"], "in_queue": st["stage_queue_us"] - st["stage_push_us"],
+                           "preparation": st["stage_prep_us"], "kernel_and_copy": st["stage_kernel_copy_us"],
+                           "integration": st["stage_integration_us"]},
+        "stages_max_thread_s": {"push": st["wait_push_s_max"], "in_queue": st["wait_queue_s_max"],
+                                "preparation": st["wait_prep_s_max"], "kernel_and_copy": st["wait_kernel_copy_s_max"],
+                                "integration": st["wait_integration_s_max"]},
         "label_mismatches": res["mismatches"], "errors": res["errors"],
         "critical_points": {"minima": res["minima"], "maxima": res["maxima"], "saddles": res["saddles"]},
     }
-    log("plain serving baseline")
-    pctx = gale.Context(device=0, mode="direct", form="plain", block_threads=args.block_threads)
-    pctx.load(mesh.tets, mesh.cluster, mesh.nclusters)
-    pres = gale.consumer_run(pctx, mesh.tets, field, order, threads=args.consumers)
-    pctx.close()
-    out["plain"] = {"accesses": pres["accesses"], "wall_s": pres["wall_s"],
-                    "accesses_per_s": pres["accesses"] / pres["wall_s"],
-                    "p50_us": pres["lat_p50_us"], "p99_us": pres["lat_p99_us"], "mean_us": pres["lat_mean_us"],
-                    "label_mismatches": pres["mismatches"], "errors": pres["errors"]}
+    if plain:
+        log("serving: plain per-cluster baseline")
+        pctx = gale.Context(device=0, mode="direct", form="plain")
+        pctx.load(mesh.tets, mesh.cluster, mesh.nclusters)
+        pres = gale.consumer_run(pctx, mesh.tets, field, order, threads=consumers)
+        pctx.close()
+        out["plain"] = {"accesses": pres["accesses"], "wall_s": pres["wall_s"],
+                        "accesses_per_s": pres["accesses"] / pres["wall_s"],
+                        "p50_us": pres["lat_p50_us"], "p99_us": pres["lat_p99_us"], "mean_us": pres["lat_mean_us"],
+                        "label_mismatches": pres["mismatches"], "errors": pres["errors"]}
     return out
+
+
+def summarize_profile(out_md, title, cmd_kt, kt_dir, cmd_fetch=None, fetch_dir=None, cmd_write=None,
+                      write_dir=None, kernel_ms=None):
+    """Turn rocprofv3 CSV output into a committed text summary: per-kernel
+    statistics, the span of each step's persistent launches (first start to
+    last end, from the kernel trace), and HBM traffic per step from
+    FETCH_SIZE / WRITE_SIZE scaled by a plain copy of known size."""
+    lines = ["# " + title, "", "Command: `%s`" % cmd_kt, "", "| kernel | calls | total ms | avg us | min us | max us |",
+             "|---|---|---|---|---|---|"]
+    for fn in glob.glob(os.path.join(kt_dir, "**", "*kernel_stats.csv"), recursive=True):
+        for r in csv.DictReader(open(fn)):
+            name = r.get("Name") or r.get("KernelName") or ""
+            lines.append("| %s | %d | %.3f | %.1f | %.1f | %.1f |" % (
+                name[:90], int(float(r.get("Calls", 0))), float(r.get("TotalDurationNs", 0)) / 1e6,
+                float(r.get("AverageNs", 0)) / 1e3, float(r.get("MinNs", 0)) / 1e3, float(r.get("MaxNs", 0)) / 1e3))
+    # steps: runs of persistent launches separated by the zero kernel that starts each graph replay
+    spans = []
+    for fn in glob.glob(os.path.join(kt_dir, "**", "*kernel_trace.csv"), recursive=True):
+        rows = sorted(csv.DictReader(open(fn)), key=lambda r: int(r["Start_Timestamp"]))
+        cur = None
+        for r in rows:
+            name = r["Kernel_Name"]
+            if "gale_zero_kernel" in name:
+                if cur:
+                    spans.append(cur)
+                cur = [None, None, 0]
+            elif "gale_persistent_kernel" in name and cur is not None:
+                s, e = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+                cur[0] = s if cur[0] is None else min(cur[0], s)
+                cur[1] = e if cur[1] is None else max(cur[1], e)
+                cur[2] += 1
+        if cur and cur[0] is not None:
+            spans.append(cur)
+    spans = [s for s in spans if s[0] is not None]
+    if spans:
+        d = [(s[1] - s[0]) / 1e6 for s in spans]
+        lines += ["", "Steps (graph replays): %d; persistent launches per step: %s; span of a step's launches "
+                  "(first start to last end) mean %.3f ms, min %.3f, max %.3f." % (
+                      len(spans), sorted(set(s[2] for s in spans)), sum(d) / len(d), min(d), max(d))]
+        if kernel_ms:
+            lines.append("HIP events around the same launches in the benchmark's own run: %.3f ms." % kernel_ms)
+    if fetch_dir and write_dir:
+        per = {}
+        for tag, dd in (("fetch", fetch_dir), ("write", write_dir)):
+            vals = {}
+            for fn in glob.glob(os.path.join(dd, "**", "*counter_collection.csv"), recursive=True):
+                for r in csv.DictReader(open(fn)):
+                    vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+            per[tag] = vals
+        copy = [k for k in per["fetch"] if "neg" in k.lower()]
+        if copy and copy[0] in per["write"]:
+            cf = sum(per["fetch"][copy[0]]) / len(per["fetch"][copy[0]])
+            cw = sum(per["write"][copy[0]]) / len(per["write"][copy[0]])
+            ff, wf = COPY_BYTES / (cf * 1024.0), COPY_BYTES / (cw * 1024.0)
+            lines += ["", "## HBM traffic (rocprofv3 --pmc, KiB per dispatch)", "",
+                      "Commands: `%s` and `%s`" % (cmd_fetch, cmd_write), "",
+                      "| kernel | dispatches | FETCH_SIZE KiB (mean) | WRITE_SIZE KiB (mean) |", "|---|---|---|---|"]
+            tot = 0.0
+            for k in sorted(per["fetch"]):
+                if "gale_persistent_kernel" not in k or k not in per["write"]:
+                    continue
+                f, w = per["fetch"][k], per["write"][k]
+                lines.append("| %s | %d | %.0f | %.0f |" % (k[:90], len(f), sum(f) / len(f), sum(w) / len(w)))
+                tot += sum(f) / len(f) * 1024 * ff + sum(w) / len(w) * 1024 * wf
+            lines += ["| copy of %d MiB (%s) | | %.0f | %.0f |" % (COPY_BYTES >> 20, copy[0][:40], cf, cw), "",
+                      "Scale factors (known bytes / counter): fetch %.3f, write %.3f." % (ff, wf),
+                      "HBM traffic of one step (one dispatch of each persistent kernel): %.1f MB." % (tot / 1e6)]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", out_md)
 
 
 def main():
@@ -223,32 +274,38 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--block-threads", type=int, default=1024)
-    ap.add_argument("--lds-bytes", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--no-graph", action="store_true", help="one gale_build per step instead of a graph replay")
-    ap.add_argument("--autotune", type=int, default=-1,
-                    help="pick the launch classes by timing (default: on for the refined configs 3-5)")
+    ap.add_argument("--tune-table", default=TUNE_TABLE, help="tune table read at load and written by autotune")
+    ap.add_argument("--retune", action="store_true", help="run the autotuner even if the table has an entry")
     ap.add_argument("--consumers", type=int, default=40)
     ap.add_argument("--serving-clusters", type=int, default=-1,
-                    help="clusters the consumers' cursor walks (default: all on the lattices, 4096 on refined meshes)")
-    ap.add_argument("--serving-budget-mb", type=int, default=0,
-                    help="HBM cache budget of the serving leg; 0 = half of one full pass's block bytes")
+                    help="clusters the consumers' cursor walks (default: all on the lattices, 24,000 on the "
+                         "refined meshes, enough to overflow a 4 GB cache)")
+    ap.add_argument("--budgets-gb", default="",
+                    help="comma-separated HBM cache budgets of the serving leg (default: 4 on configs 3-4, "
+                         "8,32,128 on config 5, half a pass's block bytes on the lattices)")
+    ap.add_argument("--front-ends", default="single,per_relation",
+                    help="serving front ends to run (the first one also runs the plain baseline)")
+    ap.add_argument("--prefetch", type=int, default=0, help="prefetch_depth of the serving leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one %d MiB device copy (reference for the HBM byte counters)" % (COPY_BYTES >> 20))
-    ap.add_argument("--summarize-profile", nargs=8, metavar=("KT", "FETCH", "WRITE", "MD", "JSON", "CMD_KT",
-                                                           "CMD_FETCH", "CMD_WRITE"))
+    ap.add_argument("--summarize-profile", nargs="+", metavar="ARG",
+                    help="OUT_MD TITLE CMD_KT KT_DIR [CMD_FETCH FETCH_DIR CMD_WRITE WRITE_DIR [KERNEL_MS]]")
     args = ap.parse_args()
     if args.summarize_profile:
-        summarize_profile(*args.summarize_profile)
+        a = args.summarize_profile
+        kms = float(a[8]) if len(a) > 8 else None
+        summarize_profile(a[0], a[1], a[2], a[3], *(a[4:8] if len(a) >= 8 else []), kernel_ms=kms)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: the library has no multi-GPU path (clusters are independent, so "
-              "Morton ranges of cluster ids would go to separate GPUs with no per-request collective). "
-              "Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU.  Clusters are independent, so several GPUs would each take a "
+              "contiguous Morton range of cluster ids balanced by star + halo size, load only that range's "
+              "streams, and serve requests routed by owner with no per-request collective; this build has no "
+              "such path.  Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -262,9 +319,12 @@ def main():
     stream = torch.cuda.Stream()
 
     log("generating config", args.config)
+    tg = time.perf_counter()
     mesh = meshgen.config(args.config)
+    gen_s = time.perf_counter() - tg
     nv, nt, ncl = mesh.nv, mesh.nt, mesh.nclusters
     ids = np.arange(ncl, dtype=np.int32)
+    log("generated in %.1f s: %d vertices, %d tetrahedra, %d clusters" % (gen_s, nv, nt, ncl))
 
     if args.copy_calibration:
         # a plain read+write kernel of known size: dst = -src over COPY_BYTES
@@ -275,40 +335,44 @@ def main():
         del src, dst
 
     ctx = gale.Context(device=0, mode="direct", form="batched", block_threads=args.block_threads,
-                       lds_bytes=args.lds_bytes, stream=stream.cuda_stream)
+                       stream=stream.cuda_stream, tune_table_path=args.tune_table)
     log("loading")
     ctx.load(mesh.tets, mesh.cluster, ncl)
     st0 = ctx.stats()
-    mesh_bytes = st0["device_mesh_bytes"]
+    log("loaded in %.1f s" % st0["load_seconds"])
     tuned = None
-    if args.autotune == 1 or (args.autotune < 0 and args.config >= 3):
+    if args.config >= 3 and (args.retune or not st0["tune_applied"]):
         log("autotune")
         chosen, cand = ctx.autotune(ids, 7, reps=2)
-        tuned = {"launch_classes": chosen, "candidates_ms": {str(k): v for k, v in cand.items()},
-                 "global_cu_share": ctx.stats()["global_cu_share"]}
-    use_graph = not args.no_graph
-    graph = ctx.graph_create(ids, 7) if use_graph else None
+        tuned = {"source": "gale_autotune in this run", "launch_classes": chosen,
+                 "candidates_ms": {str(k): v for k, v in cand.items()}}
+    elif st0["tune_applied"]:
+        tuned = {"source": "tune table"}
+    if tuned is not None:
+        tuned.update({"table": os.path.relpath(args.tune_table, ROOT),
+                      "global_cu_share": ctx.stats()["global_cu_share"]})
+        try:
+            for e in json.load(open(args.tune_table))["entries"]:
+                if e["nv"] == nv and e["nt"] == nt and e["nclusters"] == ncl and e["rel_mask"] == 7:
+                    tuned["entry"] = e
+        except (OSError, ValueError, KeyError):
+            pass
+    graph = ctx.graph_create(ids, 7)
 
-    def step():
-        return ctx.graph_launch(graph) if use_graph else ctx.build(ids, 7, "batched")
-
-    # warmup (a graph's steps share its buffer: release each before the next)
     log("warmup")
     for _ in range(max(1, args.warmup)):
-        t = step()
+        t = ctx.graph_launch(graph)
         ctx.poll(t)
         ctx.release(t)
     e_before = ctx.stats()["entries_built"]
 
-    # timed region: K steps back to back on the context stream.  The library
-    # records HIP events around each step's launches on that stream; their
-    # mean is the kernel time the roofline uses.
+    # timed region: K graph replays back to back on the context stream.  The
+    # library records HIP events around each step's launches on that stream;
+    # their mean is the kernel time the roofline uses.
     ctx.reset_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tks = []
-    for i in range(args.steps):
-        tks.append(step())
+    tks = [ctx.graph_launch(graph) for _ in range(args.steps)]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     for t in tks:
@@ -317,23 +381,26 @@ def main():
     entries_step = (st_t["entries_built"] - e_before) // args.steps
     for t in tks:
         ctx.release(t)
-    if graph is not None:
-        ctx.graph_destroy(graph)
+    ctx.graph_destroy(graph)
     ms_kernel = st_t["kernel_ms_total"] / max(1, st_t["timed_launches"])
     ms_step = wall * 1000.0 / args.steps
     value = entries_step / (ms_step / 1000.0)
-    alg_bytes = mesh_bytes + output_bytes(entries_step, nv, nt, ncl)
-    achieved = alg_bytes / (ms_kernel / 1000.0) / 1e9
+    b_alg, parts = alg_bytes(ctx, ncl, entries_step)
+    b_stream = stream_bytes(st0["device_mesh_bytes"], entries_step, nv, nt, ncl)
+    achieved = b_alg / (ms_kernel / 1000.0) / 1e9
+    log("step %.3f ms, kernels %.3f ms, %.2f G entries/s, %.1f%% of HBM peak"
+        % (ms_step, ms_kernel, value / 1e9, 100 * achieved / HBM_PEAK_GBS))
+    st = ctx.stats()
 
     plain = None
     if not args.no_plain:
         log("plain per-cluster launches")
         pctx = gale.Context(device=0, mode="direct", form="plain", block_threads=args.block_threads,
-                            lds_bytes=args.lds_bytes, stream=stream.cuda_stream)
+                            stream=stream.cuda_stream)
         pctx.load(mesh.tets, mesh.cluster, ncl)
-        for t in [pctx.build(ids, 7, "plain")]:
-            pctx.poll(t)
-            pctx.release(t)
+        t = pctx.build(ids[: min(64, ncl)], 7, "plain")
+        pctx.poll(t)
+        pctx.release(t)
         torch.cuda.synchronize()
         p0 = time.perf_counter()
         t = pctx.build(ids, 7, "plain")
@@ -342,18 +409,33 @@ def main():
         pctx.release(t)
         pctx.close()
         plain = {"value": entries_step / pdt, "unit": "entries/s", "launches": 3 * ncl,
-                 "ms_per_pass": pdt * 1000.0}
+                 "ms_per_pass": pdt * 1000.0, "batched_over_plain": value / (entries_step / pdt)}
 
     serving = None
     if not args.no_serving:
-        serving = serving_leg(mesh, args, output_bytes(entries_step, nv, nt, ncl))
+        if args.budgets_gb:
+            budgets = [int(float(x) * (1 << 30)) for x in args.budgets_gb.split(",")]
+        elif args.config == 5:
+            budgets = [8 << 30, 32 << 30, 128 << 30]
+        elif args.config >= 3:
+            budgets = [4 << 30]
+        else:
+            budgets = [stream_bytes(0, entries_step, nv, nt, ncl) // 2]
+        ncur = args.serving_clusters if args.serving_clusters >= 0 else (ncl if args.config <= 2 else 24000)
+        fronts = [f for f in args.front_ends.split(",") if f]
+        serving = {"workload": "the benchmark mesh with a 16-Gaussian scalar field; %d native consumer threads, "
+                               "Morton cursor, truncated Zipf(1.1) re-access, VT+VV+TT per access, critical points "
+                               "from VT and VV" % args.consumers, "runs": []}
+        for bi, b in enumerate(budgets):
+            for fi, fe in enumerate(fronts):
+                serving["runs"].append(serving_leg(mesh, b, args.consumers, ncur, fe, plain=(bi == 0 and fi == 0),
+                                                   prefetch=args.prefetch))
 
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         cpu = cpu_baseline(mesh)
 
-    st = ctx.stats()
     ctx.close()
     out = {
         "metric": "VT/VV/TT relation entries/s",
@@ -374,16 +456,20 @@ def main():
             "seed": 0,
             "entries_per_step": int(entries_step),
             "clusters": ncl,
-            "form": "batched, one hipGraph replay per step" if use_graph else "batched, one build call per step",
+            "form": "batched, one hipGraph replay per step",
             "block_threads": args.block_threads,
             "autotune": tuned,
+            "generate_seconds": gen_s,
             "load_seconds": st0["load_seconds"],
             "global_path_blocks_per_step": int(st["global_path_blocks"] // max(1, st["requests"])),
+            "hybrid_path_blocks_per_step": int(st["hybrid_path_blocks"] // max(1, st["requests"])),
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-            "alg_bytes_per_launch": int(alg_bytes), "kernel_ms": ms_kernel,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "alg_bytes_per_step": int(b_alg), "alg_bytes_parts": parts, "kernel_ms": ms_kernel,
+            "stream_bytes_per_step": int(b_stream),
+            "stream_frac": b_stream / (ms_kernel / 1000.0) / 1e9 / HBM_PEAK_GBS,
         },
         "cpu_baseline": cpu,
         "plain": plain,

@@ -72,7 +72,8 @@ typedef struct {
     int32_t  lds_bytes;           /* LDS budget per workgroup in bytes; 0 = tuned default; small values force the
                                      global-memory path (used by tests) */
     int32_t  max_inflight;        /* SERVE: batches on the GPU at once (1..8); 0 = 2 */
-    uint64_t cache_budget_bytes;  /* SERVE: bytes of device memory for resident blocks; 0 = 1 GiB */
+    uint64_t cache_budget_bytes;  /* SERVE: bytes of device memory for resident blocks; 0 = 1 GiB (or arena_bytes
+                                     when dev_arena is given) */
     int32_t  max_queue;           /* SERVE: pending requests accepted before EAGAIN; 0 = 65536 */
     int32_t  launch_classes;      /* BATCHED form: which workgroup shapes clusters may use, bit 0 = 1024 threads with
                                      the whole LDS, bit 1 = 512 threads with half, bit 2 = 256 threads with a
@@ -86,7 +87,28 @@ typedef struct {
                                      launch takes when LDS-path launch classes run beside it (it is then launched
                                      first); 0 = 1.  gale_autotune may change it.  SERVE mode runs a batch's
                                      launches one after another and always gives the global launch every CU. */
+    void    *dev_arena;           /* SERVE: borrowed device memory (e.g. the storage of a torch tensor on
+                                     `device`) that holds the HBM relation cache instead of a library allocation;
+                                     NULL = the library allocates the cache.  Must outlive the context; 256-byte
+                                     aligned.  DIRECT mode: must be NULL. */
+    uint64_t arena_bytes;         /* bytes at dev_arena (at least 1 MiB); the cache budget is then
+                                     min(arena_bytes, cache_budget_bytes) with 0 read as arena_bytes */
+    const char *tune_table_path;  /* JSON tune table, or NULL.  gale_load reads it when the file exists and
+                                     applies the entry recorded for a mesh of the same size and cluster count
+                                     (launch classes, CU share of the global launch, VV lanes per row);
+                                     gale_autotune writes its choice there.  The string is copied. */
+    int32_t  prefetch_depth;      /* SERVE: also build the next prefetch_depth clusters (by id, which is the
+                                     Morton order of the generator's clusterings) after each requested one, as
+                                     speculative cache entries evicted before any requested block (0..64; 0 =
+                                     none).  The paper's leader computes each request's following segments too,
+                                     Section 4.5. */
+    int32_t  front_end;           /* SERVE: GALE_FRONT_SINGLE (one queue, one service thread, a request's relations
+                                     built by one kernel) or GALE_FRONT_PER_RELATION (one queue and one leader
+                                     thread per relation, each building only its relation, Section 4.5) */
 } gale_config;
+
+#define GALE_FRONT_SINGLE       0
+#define GALE_FRONT_PER_RELATION 1
 
 /* A read-only view of one CSR block.  For gale_block the pointers are host
  * memory owned by the library; for gale_block_device they are device memory.
@@ -142,51 +164,107 @@ typedef struct {
     uint64_t hybrid_path_blocks;    /* of global_path_blocks, those run with their most used arrays in LDS */
     double   global_cu_share;       /* share of the CUs the global-path launch takes when LDS-path launch classes
                                        run beside it (1 unless gale_autotune chose less) */
+    /* serving: the paper's waiting-time breakdown (Section 5.3: request push, request in queue, data
+       preparation, kernel computation and transfer back, data integration), mean microseconds per request;
+       the id mapping the paper does on the host after the copy is fused into the kernel's stores here,
+       so "integration" is the time from the block copy's completion to the request being ready */
+    double   stage_push_us, stage_prep_us, stage_kernel_copy_us, stage_integration_us;
+    /* the same stages summed per submitting thread, seconds, maximum over threads (the paper's
+       aggregation for many consumers, Section 5.3) */
+    double   wait_push_s_max, wait_queue_s_max, wait_prep_s_max, wait_kernel_copy_s_max, wait_integration_s_max;
+    /* serving: speculative builds of following clusters (gale_config.prefetch_depth) */
+    uint64_t prefetch_built;        /* speculative blocks built */
+    uint64_t prefetch_hits;         /* requests that found a speculative block resident or in flight */
+    uint64_t prefetch_evicted;      /* speculative blocks evicted before any request used them */
+    uint64_t demand_evictions;      /* evictions of blocks some request had used */
+    int32_t  front_end;             /* GALE_FRONT_SINGLE or GALE_FRONT_PER_RELATION */
+    int32_t  tune_applied;          /* 1 when gale_load applied an entry of the tune table */
 } gale_stats;
 
-/* Create a context on cfg->device.  cfg may be NULL for defaults. */
+/* Sizes of one cluster's prepared lists (the per-segment internal and
+ * external tetrahedra and vertex interval of the initialization step,
+ * Section 4.3, plus this library's halo), as gale_get_cluster_info reports
+ * them. */
+typedef struct {
+    int32_t cluster;
+    int32_t nV;       /* vertices of the cluster: VT and VV rows */
+    int32_t nT;       /* tetrahedra internal to the cluster: TT rows */
+    int32_t ns;       /* tetrahedra with a vertex in the cluster (internal and external) */
+    int32_t nh;       /* halo: tetrahedra outside that set sharing a triangle with an internal one */
+    int32_t L;        /* distinct vertices of those tetrahedra and of the cluster */
+    int32_t nnzVT;    /* entries of the cluster's VT block */
+    int32_t cap_vv;   /* bound on the entries of its VV block (exact count known after a build) */
+} gale_cluster_info;
+
+/* Create a context on cfg->device (cfg may be NULL for defaults).  The
+ * context stands for the paper's producer side: it owns the leader role
+ * (batching requests and launching kernels) and the memory it preallocates
+ * (Section 4.2, overview of the consumer / leader / worker model; Section 4.5,
+ * preallocated GPU memory).  Ownership: *out belongs to the caller until
+ * gale_destroy.  Errors: EINVAL (bad field, e.g. block_threads not 256/512/1024,
+ * global_cu_share outside [0, 1], dev_arena in DIRECT mode, arena_bytes below
+ * 1 MiB, prefetch_depth outside 0..64, unknown front_end), EDEVICE (no HIP
+ * device or a runtime failure); *out is NULL on error. */
 gale_status gale_create(const gale_config *cfg, gale_ctx **out);
 
-/* Load a mesh (host arrays; copied, the caller keeps ownership).
+/* Load a mesh: the paper's input (V, T, S; here T and S, since no kernel reads
+ * coordinates) and its initialization step, which prepares per-segment
+ * internal and external tetrahedron lists and interval arrays on the CPU and
+ * copies them to GPU memory (Section 4.3, "Input data" and "Initialization").
  * tv: nt*4 vertex ids, row-major; cluster_of_vertex: nv cluster ids in
- * [0, nclusters); nv and nt at most 2^30.  Validates (EINVAL), prepares every
- * cluster's star and halo
- * stream and copies them to device memory.  May be called once per context. */
+ * [0, nclusters); nv and nt at most 2^30.  Both arrays are host memory, read
+ * during the call and copied; the caller keeps ownership.  Errors: EINVAL
+ * (id out of range, repeated vertex in a tetrahedron, nclusters <= 0),
+ * ENOMEM (device memory), ESTATE (a mesh is already loaded: once per
+ * context), EDEVICE.  When cfg.tune_table_path names an existing table with
+ * an entry for this mesh's (nv, nt, nclusters), that entry is applied. */
 gale_status gale_load(gale_ctx *ctx, int32_t nv, int64_t nt, const int32_t *tv,
                       const int32_t *cluster_of_vertex, int32_t nclusters);
 
-/* Request the relations in rel_mask for n cluster ids (duplicates allowed and
- * built once).  DIRECT mode: builds on the GPU and copies the blocks to host
- * memory before returning (the ticket is ready).  SERVE mode: queues the
- * request and returns at once; EAGAIN if the queue is full.  Thread-safe. */
+/* Request the relations in rel_mask for n cluster ids: the consumer's request
+ * for a coboundary or adjacency relation of a whole segment (Section 4.4).
+ * cluster_ids is host memory, read during the call; duplicates are allowed
+ * and built once.  DIRECT mode: builds on the GPU in cfg.form and copies the
+ * blocks to pinned host memory before returning (the ticket is ready).  SERVE
+ * mode: queues the request for the serving loop and returns at once.
+ * *ticket_out identifies the request until gale_release.  Errors: EINVAL (id
+ * out of range, mask empty or with unknown bits, NULL pointer), ESTATE (no
+ * mesh loaded, context being destroyed), EAGAIN (SERVE: queue full),
+ * ENOMEM, EDEVICE (also: context poisoned earlier).  Thread-safe. */
 gale_status gale_submit(gale_ctx *ctx, const int32_t *cluster_ids, int32_t n, uint32_t rel_mask,
                         uint64_t *ticket_out);
 
 /* Build into device memory only (no copy to the host), asynchronously on the
- * context stream, in the given form.  Returns a ticket whose blocks are read
- * with gale_block_device after gale_poll reports it ready.  DIRECT mode only. */
+ * context stream, in the given form: the kernel launch a leader issues for its
+ * batch, without the transfer back (Section 4.5; Section 4.6 for the kernels).
+ * Returns a ticket whose blocks are read with gale_block_device after
+ * gale_poll reports it ready.  DIRECT mode only (ESTATE otherwise); other
+ * errors as gale_submit. */
 gale_status gale_build(gale_ctx *ctx, const int32_t *cluster_ids, int32_t n, uint32_t rel_mask,
                        int32_t form, uint64_t *ticket_out);
 
-/* Choose the workgroup shapes for batched work by measurement (batch
- * formation with cluster buckets; Section 4.5 batches every pending request,
- * these buckets decide how each cluster of a batch runs).  Each candidate
- * value of gale_config.launch_classes (0, 2, 4, 6) builds the clusters
- * ids[0..n) with rel_mask in the BATCHED form, device only, once to warm up
- * and then `reps` times; the one with the shortest mean kernel time is kept
- * for the context's later batched work.  When the request then runs both
- * LDS-path classes and the global path, the share of the CUs the global
+/* Choose how batched work runs by measurement: the analogue of the paper's
+ * study of threads per segment, threads per block and blocks per request
+ * (Appendix A; the kernel's block and thread parameters, Section 4.5).
+ * Each candidate value of gale_config.launch_classes (0, 2, 4, 6) builds the
+ * clusters ids[0..n) with rel_mask in the BATCHED form, device only, once to
+ * warm up and then `reps` times; the one with the shortest mean kernel time
+ * is kept for the context's later batched work.  When the request then runs
+ * both LDS-path classes and the global path, the share of the CUs the global
  * launch takes (1, 0.8, 0.65, 0.5) is chosen the same way
- * (gale_stats.global_cu_share).  DIRECT mode with a mesh loaded; no
- * other call may use the context meanwhile.  chosen_out (may be NULL)
- * receives the chosen value, ms_out (may be NULL; 4 doubles) the mean
- * milliseconds of each candidate in the order above.  EINVAL, ESTATE,
- * EDEVICE as gale_build. */
+ * (gale_stats.global_cu_share).  The choice is written to cfg.tune_table_path
+ * when one was given (keyed by the mesh's nv, nt and nclusters).  DIRECT mode
+ * with a mesh loaded; no other call may use the context meanwhile.
+ * chosen_out (may be NULL) receives the chosen value, ms_out (may be NULL; 4
+ * doubles) the mean milliseconds of each candidate in the order above.
+ * Errors: EINVAL, ESTATE, EDEVICE as gale_build; ENOENT when the tune table
+ * cannot be written. */
 gale_status gale_autotune(gale_ctx *ctx, const int32_t *cluster_ids, int32_t n, uint32_t rel_mask, int32_t reps,
                           int32_t *chosen_out, double *ms_out);
 
 /* hipGraph-captured submit for a request built again and again (the same
- * clusters and relations, e.g. every step of an iterative analysis).
+ * clusters and relations, e.g. every step of an iterative analysis); the
+ * leader's batched launch of Section 4.5 replayed from a HIP graph.
  * gale_graph_create lays the request's blocks out in one device buffer, copies
  * its work list to the device and captures its launches (queue reset and the
  * persistent kernels of every workgroup shape) in a HIP graph; DIRECT mode.
@@ -195,39 +273,73 @@ gale_status gale_autotune(gale_ctx *ctx, const int32_t *cluster_ids, int32_t n, 
  * gale_release; all tickets of one graph share its buffer, so a ticket's
  * blocks are valid until the next gale_graph_launch of the same graph.
  * gale_graph_destroy waits for the context stream and frees the graph and its
- * buffer (its tickets must be released first).  EINVAL, ESTATE, ENOENT
- * (unknown graph), ENOMEM, EDEVICE. */
+ * buffer; it returns ESTATE, and frees nothing, while a ticket of the graph is
+ * not released.  Errors: EINVAL, ESTATE, ENOENT (unknown graph), ENOMEM,
+ * EDEVICE. */
 gale_status gale_graph_create(gale_ctx *ctx, const int32_t *cluster_ids, int32_t n, uint32_t rel_mask,
                               uint64_t *graph_out);
 gale_status gale_graph_launch(gale_ctx *ctx, uint64_t graph, uint64_t *ticket_out);
 gale_status gale_graph_destroy(gale_ctx *ctx, uint64_t graph);
 
-/* Wait up to timeout_ns (0 = just test, <0 = forever) for the ticket.
- * OK = ready; EAGAIN = not yet; ENOENT = unknown ticket. */
+/* Wait up to timeout_ns (0 = just test, <0 = forever) for the ticket: the
+ * consumer waiting on its semaphore until the leader has the relation ready
+ * (Section 4.2).  OK = ready; EAGAIN = not yet; ENOENT = unknown ticket; the
+ * request's own error (ENOMEM, EDEVICE, ESTATE after gale_destroy began)
+ * otherwise.  Thread-safe. */
 gale_status gale_poll(gale_ctx *ctx, uint64_t ticket, int64_t timeout_ns);
 
-/* Host view of one block of a ready ticket (submitted with gale_submit). */
+/* Host view of one block of a ready ticket made with gale_submit: the
+ * relation in the form the consumer reads, already in original ids (the
+ * paper's local-to-global mapping after the transfer, Section 4.5).  *out
+ * points into library-owned pinned host memory valid until
+ * gale_release(ticket).  Errors: EINVAL (rel not one bit, NULL), EAGAIN (not
+ * ready), ENOENT (cluster or relation not in the ticket), ESTATE (ticket made
+ * with gale_build), the request's own error. */
 gale_status gale_block(gale_ctx *ctx, uint64_t ticket, int32_t cluster_id, uint32_t rel, gale_csr *out);
 
-/* Device view of one block of a ready ticket made with gale_build. */
+/* Device view of one block of a ready ticket made with gale_build or
+ * gale_graph_launch (the relation array in GPU memory, Section 4.5).  The
+ * pointers are device memory owned by the library, valid until
+ * gale_release(ticket).  DIRECT mode.  Errors as gale_block. */
 gale_status gale_block_device(gale_ctx *ctx, uint64_t ticket, int32_t cluster_id, uint32_t rel, gale_csr *out);
 
-/* Release a ticket: its views become invalid and its memory is reused. */
+/* Release a ticket: its views become invalid and its memory is reused, as the
+ * paper reuses its preallocated per-consumer memory (Section 4.5).  Waits for
+ * the ticket's work if it is still running.  Errors: ENOENT (unknown or
+ * already released). */
 gale_status gale_release(gale_ctx *ctx, uint64_t ticket);
 
+/* Counters and latency figures of the context, including the paper's
+ * waiting-time breakdown per request (Section 5.3) and the queue depth seen
+ * when requests are admitted (Section 4.5 reports its mean and spread).
+ * Named gale_get_stats because the struct typedef takes the name gale_stats
+ * in C.  *out is caller memory, filled completely.  Errors: EINVAL. */
 gale_status gale_get_stats(gale_ctx *ctx, gale_stats *out);
 
-/* Set the serving-loop latency statistics back to zero (between benchmark phases). */
+/* Set the latency, stage and cache statistics back to zero (between benchmark
+ * phases; Section 5.3 measures each run separately).  Errors: EINVAL. */
 gale_status gale_reset_stats(gale_ctx *ctx);
 
-/* The hipStream_t the context launches DIRECT-mode work on. */
+/* The hipStream_t the context launches DIRECT-mode work on (the borrowed one,
+ * or the library's); NULL for a NULL context.  Borrowed by the caller. */
 void *gale_stream(gale_ctx *ctx);
 
+/* Sizes of cluster `cluster` of the loaded mesh (see gale_cluster_info):
+ * what the initialization step prepared for that segment (Section 4.3).
+ * *out is caller memory.  Errors: EINVAL (NULL, cluster out of range),
+ * ESTATE (no mesh loaded).  Thread-safe. */
+gale_status gale_get_cluster_info(gale_ctx *ctx, int32_t cluster, gale_cluster_info *out);
+
+/* Text of a status code (static storage). */
 const char *gale_strerror(gale_status s);
-/* Detail of the last error raised on the calling thread ("" if none). */
+/* Detail of the last error raised on the calling thread ("" if none); valid
+ * until the thread's next failing call. */
 const char *gale_last_error(void);
 
-/* Drain in-flight work, fail pending polls with ESTATE, free everything. */
+/* Drain in-flight work, fail pending and waiting requests with ESTATE, wait
+ * until no other thread is inside gale_poll / gale_release on this context,
+ * and free everything the context owns (the end of the paper's producer
+ * threads, Section 4.2).  Borrowed streams and arenas are not freed. */
 void gale_destroy(gale_ctx *ctx);
 
 #ifdef __cplusplus

@@ -12,6 +12,8 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -117,6 +119,26 @@ void setup_classes(gale_ctx *ctx, int mask) {
     ctx->class_mask = mask;
 }
 
+// Global-path launches: bt threads per workgroup, as many workgroups per CU as
+// the registers allow, each with its share of the CU's LDS for the hybrid
+// form (none when bit 3 of the configured launch classes keeps every array in
+// global memory).
+void setup_global(gale_ctx *ctx, int bt) {
+    ctx->glob_bt = bt;
+    int occ = 0;
+    hipError_t e = persistent_occupancy(bt, false, 0, &occ);
+    if (e != hipSuccess || occ <= 0) occ = 1;
+    ctx->glob_lds = 0;
+    if (!(ctx->cfg.launch_classes & 8)) {
+        int64_t g = ctx->shared_per_block / occ - ctx->static_lds;
+        g = std::min<int64_t>(g, ctx->lds_budget) / 16 * 16;
+        ctx->glob_lds = std::max<int64_t>(g, 0);
+    }
+    int occ2 = 0;
+    e = persistent_occupancy(bt, false, (size_t)ctx->glob_lds, &occ2);
+    ctx->grid_glob = ctx->num_cus * ((e != hipSuccess || occ2 <= 0) ? 1 : occ2);
+}
+
 // The workgroup shape of an item: the smallest (last) launch class whose LDS
 // plan fits, or -1 for the global-workspace path.
 int item_class(const gale_ctx *ctx, const WorkItem &it) {
@@ -134,8 +156,8 @@ int64_t workspace_bytes(const gale_ctx *ctx, const std::vector<WorkItem> &items,
     int ng = 0;
     for (const WorkItem &it : items) {
         if (item_class(ctx, it) < 0) {
-            const Plan gp = ws_plan(ctx->meta[it.cluster], it.mask, ctx->block_threads);
-            const Plan hp = hyb_plan(ctx->meta[it.cluster], it.mask, ctx->glob_lds, ctx->block_threads);
+            const Plan gp = ws_plan(ctx->meta[it.cluster], it.mask, ctx->glob_bt);
+            const Plan hp = hyb_plan(ctx->meta[it.cluster], it.mask, ctx->glob_lds, ctx->glob_bt);
             need = std::max<int64_t>(need, hp.ok ? hp.ws_bytes : gp.bytes);
             ++ng;
         }
@@ -194,7 +216,7 @@ gale_status launch_batch(gale_ctx *ctx, int form, int32_t *d_out, int32_t *d_hdr
         for (int j = 0; j < n_glob && e == hipSuccess; ++j, ++i) {
             a.items = d_items + i;
             a.nitems = 1;
-            e = launch_items(a, false, ctx->block_threads, 1, (size_t)ctx->glob_lds, st);
+            e = launch_items(a, false, ctx->glob_bt, 1, (size_t)ctx->glob_lds, st);
             ctx->n_launches++;
         }
     } else {
@@ -238,7 +260,7 @@ gale_status launch_batch(gale_ctx *ctx, int form, int32_t *d_out, int32_t *d_hdr
                 e = launch_persistent(a, true, lc.bt, std::min<int>(l.n, lc.grid), (size_t)lc.budget, s2);
             } else {
                 a.lds_budget = (int32_t)ctx->glob_lds;
-                e = launch_persistent(a, false, ctx->block_threads, std::min<int>(l.n, gg), (size_t)ctx->glob_lds, s2);
+                e = launch_persistent(a, false, ctx->glob_bt, std::min<int>(l.n, gg), (size_t)ctx->glob_lds, s2);
             }
             ctx->n_launches++;
             if (e == hipSuccess && use_aux && li > 0) {
@@ -253,12 +275,12 @@ gale_status launch_batch(gale_ctx *ctx, int form, int32_t *d_out, int32_t *d_hdr
     return GALE_OK;
 }
 
-// Order items by launch class (then the global path), acquire the work-list
-// buffers and copy the list with zeroed queue words to the device.
-gale_status stage_items(gale_ctx *ctx, int form, const std::vector<WorkItem> &items, Buf *&dev_items,
-                        Buf *&dev_hdr, Buf *&host_items, Buf *&ws, hipStream_t st, std::vector<int> &ncls,
-                        int &n_glob, int64_t &wsb) {
-    hipError_t e;
+// Order items by launch class (then the global path), largest cluster first
+// within each: order receives the launch order, ncls the items per class
+// followed by the global launch's workgroups, n_glob the global-path items,
+// wsb the workspace bytes per global-path workgroup.  Host logic only.
+void order_items(gale_ctx *ctx, const std::vector<WorkItem> &items, std::vector<WorkItem> &order,
+                 std::vector<int> &ncls, int &n_glob, int64_t &wsb) {
     const int n = (int)items.size();
     const int ncl = (int)ctx->classes.size();
     std::vector<int> cls(n);
@@ -275,7 +297,7 @@ gale_status stage_items(gale_ctx *ctx, int form, const std::vector<WorkItem> &it
             return (int64_t)a.ns + a.nh + a.nnzVT > (int64_t)b.ns + b.nh + b.nnzVT;
         });
     };
-    std::vector<WorkItem> order;
+    order.clear();
     order.reserve(n);
     for (int c = 0; c < ncl; ++c) {
         std::vector<WorkItem> part;
@@ -300,9 +322,22 @@ gale_status stage_items(gale_ctx *ctx, int form, const std::vector<WorkItem> &it
         glob_grid = std::max(1, (int)(ctx->glob_share * ctx->grid_glob + 0.5));
     ncls.push_back(glob_grid);
     wsb = workspace_bytes(ctx, glob, nullptr);
+}
+
+// Order the items (order_items), acquire the work-list buffers and copy the
+// list with zeroed queue words to the device.
+gale_status stage_items(gale_ctx *ctx, int form, const std::vector<WorkItem> &items, Buf *&dev_items,
+                        Buf *&dev_hdr, Buf *&host_items, Buf *&ws, hipStream_t st, std::vector<int> &ncls,
+                        int &n_glob, int64_t &wsb) {
+    hipError_t e;
+    const int n = (int)items.size();
+    std::vector<WorkItem> order;
+    order_items(ctx, items, order, ncls, n_glob, wsb);
+    const int glob_grid = ncls.back();
     ctx->n_global_blocks += n_glob;
-    for (const WorkItem &it : glob)
-        if (hyb_plan(ctx->meta[it.cluster], it.mask, ctx->glob_lds, ctx->block_threads).ok) ctx->n_hybrid_blocks++;
+    for (int i = n - n_glob; i < n; ++i)
+        if (hyb_plan(ctx->meta[order[i].cluster], order[i].mask, ctx->glob_lds, ctx->glob_bt).ok)
+            ctx->n_hybrid_blocks++;
     const int slots = form == GALE_FORM_PLAIN ? 1 : std::min<int>(std::max(n_glob, 1), glob_grid);
     dev_items = ctx->dev_pool.acquire((size_t)n * sizeof(WorkItem) + 64, &e);
     dev_hdr = ctx->dev_pool.acquire((size_t)n * 32 + 64, &e);
@@ -597,6 +632,117 @@ gale_status direct_build(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t 
     return GALE_OK;
 }
 
+// ---- tune table --------------------------------------------------------------
+// A JSON file with one object per tuned (mesh, relation mask):
+//   {"gale_tune_table": 1, "entries": [
+//     {"nv": .., "nt": .., "nclusters": .., "rel_mask": .., "launch_classes": ..,
+//      "global_cu_share": .., "global_threads": .., "kernel_ms": ..,
+//      "class_ms": [.., .., .., ..]}, ...]}
+// Only this writer's format is read back: each entry object on a line of its own.
+namespace {
+
+bool json_number(const std::string &obj, const char *key, double &out) {
+    const std::string k = std::string("\"") + key + "\"";
+    const size_t p = obj.find(k);
+    if (p == std::string::npos) return false;
+    size_t q = obj.find(':', p + k.size());
+    if (q == std::string::npos) return false;
+    ++q;
+    while (q < obj.size() && (obj[q] == ' ' || obj[q] == '\t')) ++q;
+    char *end = nullptr;
+    const double v = std::strtod(obj.c_str() + q, &end);
+    if (end == obj.c_str() + q) return false;
+    out = v;
+    return true;
+}
+
+// the entry objects of a table file, one string each
+std::vector<std::string> tune_objects(const std::string &path) {
+    std::vector<std::string> objs;
+    FILE *f = std::fopen(path.c_str(), "r");
+    if (!f) return objs;
+    std::string line;
+    char buf[4096];
+    while (std::fgets(buf, sizeof(buf), f)) {
+        line += buf;
+        if (line.empty() || line.back() != '\n') continue;
+        const size_t a = line.find("{\"nv\"");
+        const size_t b = line.rfind('}');
+        if (a != std::string::npos && b != std::string::npos && b > a) objs.push_back(line.substr(a, b - a + 1));
+        line.clear();
+    }
+    std::fclose(f);
+    return objs;
+}
+
+bool entry_of(const std::string &o, TuneEntry &te) {
+    double nv, nt, ncl, mask, lc, share = 1.0, gt = 1024, kms = 0;
+    if (!json_number(o, "nv", nv) || !json_number(o, "nt", nt) || !json_number(o, "nclusters", ncl) ||
+        !json_number(o, "rel_mask", mask) || !json_number(o, "launch_classes", lc))
+        return false;
+    json_number(o, "global_cu_share", share);
+    json_number(o, "global_threads", gt);
+    json_number(o, "kernel_ms", kms);
+    te.nv = (int64_t)nv;
+    te.nt = (int64_t)nt;
+    te.ncl = (int64_t)ncl;
+    te.rel_mask = (int)mask;
+    te.launch_classes = (int)lc;
+    te.global_cu_share = share;
+    te.global_threads = (int)gt;
+    te.kernel_ms = kms;
+    return true;
+}
+
+std::string entry_json(const TuneEntry &te) {
+    char buf[512];
+    std::snprintf(buf, sizeof(buf),
+                  "{\"nv\": %lld, \"nt\": %lld, \"nclusters\": %lld, \"rel_mask\": %d, \"launch_classes\": %d, "
+                  "\"global_cu_share\": %.4f, \"global_threads\": %d, \"kernel_ms\": %.4f, "
+                  "\"class_ms\": [%.4f, %.4f, %.4f, %.4f]}",
+                  (long long)te.nv, (long long)te.nt, (long long)te.ncl, te.rel_mask, te.launch_classes,
+                  te.global_cu_share, te.global_threads, te.kernel_ms, te.class_ms[0], te.class_ms[1],
+                  te.class_ms[2], te.class_ms[3]);
+    return buf;
+}
+
+}  // namespace
+
+// The entry for a mesh of this size and cluster count; the relation mask 7
+// entry is preferred, else the first match.
+bool read_tune_entry(const std::string &path, int64_t nv, int64_t nt, int64_t ncl, TuneEntry &out) {
+    bool found = false;
+    for (const std::string &o : tune_objects(path)) {
+        TuneEntry te;
+        if (!entry_of(o, te) || te.nv != nv || te.nt != nt || te.ncl != ncl) continue;
+        if (!found || te.rel_mask == 7) out = te;
+        found = true;
+    }
+    return found;
+}
+
+// Replace (or add) the entry for the same mesh and mask; written to a
+// temporary file first and renamed over the table.
+bool write_tune_entry(const std::string &path, const TuneEntry &te) {
+    std::vector<std::string> keep;
+    for (const std::string &o : tune_objects(path)) {
+        TuneEntry x;
+        if (entry_of(o, x) && x.nv == te.nv && x.nt == te.nt && x.ncl == te.ncl && x.rel_mask == te.rel_mask)
+            continue;
+        keep.push_back(o);
+    }
+    keep.push_back(entry_json(te));
+    const std::string tmp = path + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    std::fprintf(f, "{\"gale_tune_table\": 1,\n \"entries\": [\n");
+    for (size_t i = 0; i < keep.size(); ++i)
+        std::fprintf(f, "  %s%s\n", keep[i].c_str(), i + 1 < keep.size() ? "," : "");
+    std::fprintf(f, " ]}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), path.c_str()) == 0;
+}
+
 // ---- prepared (graph) requests --------------------------------------------
 gale_status graph_create(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t mask, uint64_t *out) {
     gale_status s = check_request(ctx, ids, n, mask);
@@ -671,6 +817,7 @@ gale_status graph_launch(gale_ctx *ctx, uint64_t gid, uint64_t *ticket_out) {
         t->batch.dev_hdr = g->batch.dev_hdr;
         t->batch.host_hdr = g->batch.host_hdr;
         t->batch.borrowed = true;
+        t->graph = gid;
         t->mask = g->mask;
         t->host = false;
         t->by_cluster = g->by_cluster;
@@ -693,6 +840,7 @@ gale_status graph_launch(gale_ctx *ctx, uint64_t gid, uint64_t *ticket_out) {
             return fail(GALE_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
         }
         ctx->n_requests++;
+        g->live++;
     }
     std::lock_guard<std::mutex> g2(ctx->tick_mu);
     const uint64_t id = ++ctx->next_ticket;
@@ -706,6 +854,8 @@ gale_status graph_destroy(gale_ctx *ctx, uint64_t gid) {
     auto it = ctx->graphs.find(gid);
     if (it == ctx->graphs.end()) return fail(GALE_ENOENT, "unknown graph");
     Prepared *g = it->second;
+    if (g->live > 0)
+        return fail(GALE_ESTATE, std::to_string(g->live) + " ticket(s) of this graph are not released");
     (void)hipStreamSynchronize(ctx->stream);
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
@@ -784,6 +934,12 @@ gale_status gale_create(const gale_config *cfg_in, gale_ctx **out) {
         return fail(GALE_EINVAL, "block_threads must be 256, 512 or 1024");
     if (!(cfg.global_cu_share >= 0.0 && cfg.global_cu_share <= 1.0))
         return fail(GALE_EINVAL, "global_cu_share must be in [0, 1]");
+    if (cfg.dev_arena && cfg.mode != GALE_MODE_SERVE) return fail(GALE_EINVAL, "dev_arena is for SERVE mode only");
+    if (cfg.dev_arena && cfg.arena_bytes < (1ull << 20)) return fail(GALE_EINVAL, "arena_bytes must be >= 1 MiB");
+    if (cfg.dev_arena && ((uintptr_t)cfg.dev_arena & 255u)) return fail(GALE_EINVAL, "dev_arena must be 256-byte aligned");
+    if (cfg.prefetch_depth < 0 || cfg.prefetch_depth > 64) return fail(GALE_EINVAL, "prefetch_depth must be in 0..64");
+    if (cfg.front_end != GALE_FRONT_SINGLE && cfg.front_end != GALE_FRONT_PER_RELATION)
+        return fail(GALE_EINVAL, "unknown front_end");
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || ndev <= 0) return fail(GALE_EDEVICE, "no HIP device");
@@ -792,6 +948,8 @@ gale_status gale_create(const gale_config *cfg_in, gale_ctx **out) {
     if (e != hipSuccess) return fail(GALE_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
     auto *ctx = new gale_ctx();
     ctx->cfg = cfg;
+    if (cfg.tune_table_path) ctx->tune_path = cfg.tune_table_path;
+    ctx->cfg.tune_table_path = nullptr;  // the copy above is the one used
     ctx->glob_share = cfg.global_cu_share > 0.0 ? cfg.global_cu_share : 1.0;
     ctx->dev_pool.pinned = false;
     ctx->pin_pool.pinned = true;
@@ -825,19 +983,7 @@ gale_status gale_create(const gale_config *cfg_in, gale_ctx **out) {
     ctx->static_lds = static_lds;
     ctx->shared_per_block = (int64_t)prop.sharedMemPerBlock;
     setup_classes(ctx, cfg.launch_classes);
-    // global path: as many workgroups per CU as without LDS, each with its
-    // share of the LDS for the hybrid form
-    occ = 0;
-    e = persistent_occupancy(ctx->block_threads, false, 0, &occ);
-    if (e != hipSuccess || occ <= 0) occ = 1;
-    if (!(cfg.launch_classes & 8)) {
-        int64_t g = ctx->shared_per_block / occ - static_lds;
-        g = std::min<int64_t>(g, ctx->lds_budget) / 16 * 16;
-        ctx->glob_lds = std::max<int64_t>(g, 0);
-    }
-    int occ2 = 0;
-    e = persistent_occupancy(ctx->block_threads, false, (size_t)ctx->glob_lds, &occ2);
-    ctx->grid_glob = ctx->num_cus * ((e != hipSuccess || occ2 <= 0) ? 1 : occ2);
+    setup_global(ctx, ctx->block_threads);
     if (cfg.mode == GALE_MODE_DIRECT) {
         // streams for the launches of one batch beyond the first (classes and
         // the global path run side by side), default priority
@@ -908,6 +1054,16 @@ gale_status gale_load(gale_ctx *ctx, int32_t nv, int64_t nt, const int32_t *tv, 
     ctx->ncl = ncl;
     ctx->loaded = true;
     ctx->load_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (!ctx->tune_path.empty()) {
+        TuneEntry te;
+        if (read_tune_entry(ctx->tune_path, nv, nt, ncl, te)) {
+            setup_classes(ctx, te.launch_classes);
+            if (ctx->block_threads == 1024 && (te.global_threads == 512 || te.global_threads == 1024))
+                setup_global(ctx, te.global_threads);
+            if (te.global_cu_share > 0.0 && te.global_cu_share <= 1.0) ctx->glob_share = te.global_cu_share;
+            ctx->tune_applied = true;
+        }
+    }
     if (ctx->cfg.mode == GALE_MODE_SERVE) {
         s = serve_start(ctx);
         if (s) return s;
@@ -997,6 +1153,11 @@ gale_status gale_release(gale_ctx *ctx, uint64_t ticket) {
     if (!t->ready) (void)hipEventSynchronize(t->done);
     if (t->done) (void)hipEventDestroy(t->done);
     destroy_ticket_events(t);
+    if (t->graph) {
+        std::lock_guard<std::mutex> g(ctx->direct_mu);
+        auto it = ctx->graphs.find(t->graph);
+        if (it != ctx->graphs.end()) it->second->live--;
+    }
     for (Buf *b : t->batch.extra) ctx->dev_pool.release(b);
     release_batch(ctx, t->batch);
     delete t;
@@ -1010,6 +1171,8 @@ gale_status gale_autotune(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t
     if (!ctx) return fail(GALE_EINVAL, "ctx is NULL");
     if (ctx->cfg.mode != GALE_MODE_DIRECT) return fail(GALE_ESTATE, "autotune needs a DIRECT mode context");
     if (reps < 1) return fail(GALE_EINVAL, "reps must be >= 1");
+    gale_status st = check_request(ctx, ids, n, mask);
+    if (st) return st;
     const int candidates[4] = {0, 2, 4, 6};
     double ms[4] = {0, 0, 0, 0};
     uint64_t saved_n;
@@ -1020,7 +1183,6 @@ gale_status gale_autotune(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t
         saved_ms = ctx->kernel_ms;
     }
     int best = -1;
-    gale_status st = GALE_OK;
     // mean kernel milliseconds of the request under the current settings
     auto time_it = [&]() -> double {
         for (int r = 0; r <= reps && st == GALE_OK; ++r) {
@@ -1038,7 +1200,9 @@ gale_status gale_autotune(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t
         return ctx->n_timed ? ctx->kernel_ms / (double)ctx->n_timed : 0.0;
     };
     const double saved_share = ctx->glob_share;
+    const int saved_bt = ctx->glob_bt;
     ctx->glob_share = 1.0;
+    // 1. workgroup shapes (launch classes)
     for (int ci = 0; ci < 4 && st == GALE_OK; ++ci) {
         {
             std::lock_guard<std::mutex> g(ctx->direct_mu);
@@ -1051,33 +1215,43 @@ gale_status gale_autotune(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t
         std::lock_guard<std::mutex> g(ctx->direct_mu);
         setup_classes(ctx, best >= 0 ? candidates[best] : ctx->cfg.launch_classes);
     }
-    // then the global launch's share of the CUs, when the request runs both
-    // LDS-path classes and the global path
+    double best_ms = best >= 0 ? ms[best] : 0.0;
+    // 2. and 3. for requests with clusters on the global path: its workgroup
+    // size, then its share of the CUs when LDS-path classes run beside it
+    int nglob = 0;
     if (st == GALE_OK) {
-        int nglob = 0;
         for (int32_t i = 0; i < n; ++i) {
-            if (ids[i] < 0 || ids[i] >= ctx->ncl) continue;
             WorkItem it{};
             it.cluster = ids[i];
             it.mask = mask;
             nglob += item_class(ctx, it) < 0;
         }
-        if (nglob > 0 && nglob < n) {
-            const double shares[3] = {0.8, 0.65, 0.5};
-            double best_ms = ms[best];
-            double best_share = 1.0;
-            for (int si = 0; si < 3 && st == GALE_OK; ++si) {
-                ctx->glob_share = shares[si];
-                const double t = time_it();
-                if (st == GALE_OK && t < best_ms) {
-                    best_ms = t;
-                    best_share = shares[si];
-                }
-            }
-            ctx->glob_share = best_share;
-        }
     }
-    if (st != GALE_OK) ctx->glob_share = saved_share;
+    if (st == GALE_OK && nglob > 0 && ctx->block_threads == 1024) {
+        setup_global(ctx, 512);
+        const double t = time_it();
+        if (st == GALE_OK && t < best_ms)
+            best_ms = t;
+        else
+            setup_global(ctx, 1024);
+    }
+    if (st == GALE_OK && nglob > 0 && nglob < n) {
+        const double shares[3] = {0.8, 0.65, 0.5};
+        double best_share = 1.0;
+        for (int si = 0; si < 3 && st == GALE_OK; ++si) {
+            ctx->glob_share = shares[si];
+            const double t = time_it();
+            if (st == GALE_OK && t < best_ms) {
+                best_ms = t;
+                best_share = shares[si];
+            }
+        }
+        ctx->glob_share = best_share;
+    }
+    if (st != GALE_OK) {
+        ctx->glob_share = saved_share;
+        setup_global(ctx, saved_bt);
+    }
     {
         std::lock_guard<std::mutex> g(ctx->direct_mu);
         ctx->n_timed = saved_n;
@@ -1087,6 +1261,20 @@ gale_status gale_autotune(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t
     if (chosen_out) *chosen_out = candidates[best];
     if (ms_out)
         for (int i = 0; i < 4; ++i) ms_out[i] = ms[i];
+    if (!ctx->tune_path.empty()) {
+        TuneEntry te;
+        te.nv = ctx->nv;
+        te.nt = ctx->nt;
+        te.ncl = ctx->ncl;
+        te.rel_mask = (int)mask;
+        te.launch_classes = candidates[best];
+        te.global_cu_share = ctx->glob_share;
+        te.global_threads = ctx->glob_bt;
+        te.kernel_ms = best_ms;
+        for (int i = 0; i < 4; ++i) te.class_ms[i] = ms[i];
+        if (!write_tune_entry(ctx->tune_path, te))
+            return fail(GALE_ENOENT, "cannot write the tune table " + ctx->tune_path);
+    }
     return GALE_OK;
 }
 
@@ -1126,6 +1314,8 @@ gale_status gale_get_stats(gale_ctx *ctx, gale_stats *out) {
     out->hybrid_path_blocks = ctx->n_hybrid_blocks;
     out->global_cu_share = ctx->glob_share;
     out->tt_exhaustive_blocks = ctx->n_tt_exhaustive;
+    out->front_end = ctx->cfg.front_end;
+    out->tune_applied = ctx->tune_applied ? 1 : 0;
     out->entries_delivered = ctx->n_delivered;
     out->bytes_d2h = ctx->n_bytes_d2h;
     {
@@ -1134,6 +1324,22 @@ gale_status gale_get_stats(gale_ctx *ctx, gale_stats *out) {
         out->kernel_ms_total = ctx->kernel_ms;
     }
     if (ctx->cfg.mode == GALE_MODE_SERVE) serve_stats(ctx, out);
+    return GALE_OK;
+}
+
+gale_status gale_get_cluster_info(gale_ctx *ctx, int32_t cluster, gale_cluster_info *out) {
+    if (!ctx || !out) return fail(GALE_EINVAL, "NULL argument");
+    if (!ctx->loaded) return fail(GALE_ESTATE, "no mesh loaded");
+    if (cluster < 0 || cluster >= ctx->ncl) return fail(GALE_EINVAL, "cluster id out of range");
+    const ClusterMeta &m = ctx->meta[cluster];
+    out->cluster = cluster;
+    out->nV = m.nV;
+    out->nT = m.nT;
+    out->ns = m.ns;
+    out->nh = m.nh;
+    out->L = m.L;
+    out->nnzVT = m.nnzVT;
+    out->cap_vv = m.cap_vv;
     return GALE_OK;
 }
 

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libgale.so")
 REL_VT, REL_VV, REL_TT, REL_ALL = 1, 2, 4, 7
 FORM_PLAIN, FORM_BATCHED = 0, 1
 MODE_DIRECT, MODE_SERVE = 0, 1
+FRONT_SINGLE, FRONT_PER_RELATION = 0, 1
 
 OK, EINVAL, ENOMEM, EAGAIN, ENOENT, ESTATE, EDEVICE = 0, -1, -2, -3, -4, -5, -6
 _NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EAGAIN", -4: "ENOENT", -5: "ESTATE", -6: "EDEVICE"}
@@ -27,7 +28,8 @@ class GaleConfig(C.Structure):
         ("device", C.c_int32), ("mode", C.c_int32), ("form", C.c_int32), ("block_threads", C.c_int32),
         ("lds_bytes", C.c_int32), ("max_inflight", C.c_int32), ("cache_budget_bytes", C.c_uint64),
         ("max_queue", C.c_int32), ("launch_classes", C.c_int32), ("hip_stream", C.c_void_p),
-        ("global_cu_share", C.c_double),
+        ("global_cu_share", C.c_double), ("dev_arena", C.c_void_p), ("arena_bytes", C.c_uint64),
+        ("tune_table_path", C.c_char_p), ("prefetch_depth", C.c_int32), ("front_end", C.c_int32),
     ]
 
 
@@ -56,7 +58,17 @@ class GaleStats(C.Structure):
         ("stage_queue_us", C.c_double), ("stage_build_us", C.c_double), ("stage_copy_us", C.c_double),
         ("timed_launches", C.c_uint64), ("kernel_ms_total", C.c_double), ("hybrid_path_blocks", C.c_uint64),
         ("global_cu_share", C.c_double),
+        ("stage_push_us", C.c_double), ("stage_prep_us", C.c_double), ("stage_kernel_copy_us", C.c_double),
+        ("stage_integration_us", C.c_double),
+        ("wait_push_s_max", C.c_double), ("wait_queue_s_max", C.c_double), ("wait_prep_s_max", C.c_double),
+        ("wait_kernel_copy_s_max", C.c_double), ("wait_integration_s_max", C.c_double),
+        ("prefetch_built", C.c_uint64), ("prefetch_hits", C.c_uint64), ("prefetch_evicted", C.c_uint64),
+        ("demand_evictions", C.c_uint64), ("front_end", C.c_int32), ("tune_applied", C.c_int32),
     ]
+
+
+class GaleClusterInfo(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("cluster", "nV", "nT", "ns", "nh", "L", "nnzVT", "cap_vv")]
 
 
 class GaleConsumerCfg(C.Structure):
@@ -108,6 +120,7 @@ def load_library(path: str = LIB_PATH):
         "gale_release": ([vp, C.c_uint64], C.c_int32),
         "gale_get_stats": ([vp, C.POINTER(GaleStats)], C.c_int32),
         "gale_reset_stats": ([vp], C.c_int32),
+        "gale_get_cluster_info": ([vp, C.c_int32, C.POINTER(GaleClusterInfo)], C.c_int32),
         "gale_stream": ([vp], vp),
         "gale_strerror": ([C.c_int32], C.c_char_p),
         "gale_last_error": ([], C.c_char_p),
@@ -144,7 +157,9 @@ class Context:
 
     def __init__(self, device: int = 0, mode: str = "direct", form: str = "batched", block_threads: int = 0,
                  lds_bytes: int = 0, max_inflight: int = 0, cache_budget_bytes: int = 0, max_queue: int = 0,
-                 stream=None, launch_classes: int = 0, global_cu_share: float = 0.0):
+                 stream=None, launch_classes: int = 0, global_cu_share: float = 0.0, dev_arena=None,
+                 arena_bytes: int = 0, tune_table_path: str | None = None, prefetch_depth: int = 0,
+                 front_end: str = "single"):
         lib = load_library()
         self._lib = lib
         cfg = GaleConfig()
@@ -159,6 +174,12 @@ class Context:
         cfg.launch_classes = launch_classes
         cfg.hip_stream = stream
         cfg.global_cu_share = global_cu_share
+        cfg.dev_arena = dev_arena
+        cfg.arena_bytes = arena_bytes
+        self._tune_path = tune_table_path.encode() if tune_table_path else None
+        cfg.tune_table_path = self._tune_path
+        cfg.prefetch_depth = prefetch_depth
+        cfg.front_end = {"single": FRONT_SINGLE, "per_relation": FRONT_PER_RELATION}[front_end]
         h = C.c_void_p()
         _check(lib.gale_create(C.byref(cfg), C.byref(h)), "gale_create")
         self._h = h
@@ -270,6 +291,12 @@ class Context:
         _check(self._lib.gale_autotune(self._h, p, int(a.shape[0]), int(mask), int(reps), C.byref(chosen), ms),
                "gale_autotune")
         return chosen.value, dict(zip((0, 2, 4, 6), list(ms)))
+
+    def cluster_info(self, cluster: int) -> dict:
+        """Sizes of one cluster's prepared lists (nV, nT, ns, nh, L, nnzVT, cap_vv)."""
+        ci = GaleClusterInfo()
+        _check(self._lib.gale_get_cluster_info(self._h, int(cluster), C.byref(ci)), "gale_get_cluster_info")
+        return {name: getattr(ci, name) for name, _ in GaleClusterInfo._fields_}
 
     def reset_stats(self):
         _check(self._lib.gale_reset_stats(self._h), "gale_reset_stats")

@@ -116,8 +116,10 @@ def gather_all(get_block, ncl):
     return res
 
 
-def check_invariants(tets, nv, blocks):
-    """Raise AssertionError on any violated invariant; return the sums."""
+def check_invariants(tets, nv, blocks, manifold=True):
+    """Raise AssertionError on any violated invariant; return the sums.  On a
+    manifold mesh (every triangle in at most two tetrahedra) a TT row has at
+    most four entries, one per face."""
     tets = np.asarray(tets).reshape(-1, 4)
     nt = tets.shape[0]
     out = {}
@@ -140,7 +142,8 @@ def check_invariants(tets, nv, blocks):
             assert v in vv[u], "VV not symmetric"
     tt = dict(zip(*blocks[REL_TT]))
     for t, l in tt.items():
-        assert len(l) <= 4 or True
+        if manifold:
+            assert len(l) <= 4, "TT row with more than four entries on a manifold mesh"
         for q in l:
             assert t in tt[q], "TT not symmetric"
             assert len(set(tets[t].tolist()) & set(tets[q].tolist())) == 3, "TT pair shares no face"

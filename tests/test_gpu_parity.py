@@ -124,39 +124,117 @@ def test_config1_as_one_cluster_global_path():
         compare_all(ctx, m, orc)
 
 
-def test_config2_sampled_and_totals():
-    """128^3 lattice, 2048 clusters, built in one batched launch (the
-    benchmark's configuration): a seeded sample of clusters plus the largest
-    ones compared with the oracle; every block checked against the closed
-    forms through the sums."""
+def _device_block(ctx, tk, k, rel):
+    v = ctx.block_device(tk, int(k), rel)
+    return _d2h(v.row_ids, v.nrows), _d2h(v.offsets, v.nrows + 1), _d2h(v.entries, v.nnz)
+
+
+def _compare_graph_blocks(ctx, tk, orc, clusters, chunk=512):
+    """Every (cluster, relation) block of a graph ticket for `clusters`
+    against the oracle (built by several threads), in chunks; returns the
+    differing pairs."""
+    bad = []
+    clusters = [int(k) for k in clusters]
+    for c0 in range(0, len(clusters), chunk):
+        part = clusters[c0:c0 + chunk]
+        pairs = [(k, rel) for k in part for rel in REL]
+        exp = orc.blocks(pairs)
+        for (k, rel), e in zip(pairs, exp):
+            got = _device_block(ctx, tk, k, rel)
+            if not all(g.shape == x.shape and np.array_equal(g, x) for g, x in zip(got, e)):
+                bad.append((k, rel))
+        _say("compared", min(c0 + chunk, len(clusters)), "of", len(clusters), "clusters")
+    return bad
+
+
+def test_config2_every_block():
+    """128^3 lattice, 2048 clusters, built the way the benchmark builds it
+    (one graph replay of the batched launch): every block of every cluster
+    equals the oracle's, and the sums match the lattice's closed forms."""
     gale = _gale()
     m = meshgen.config(2)
-    _say("config 2")
+    _say("config 2", m.nv, m.nt, m.nclusters)
     with gale.Context(form="batched") as ctx:
         ctx.load(m.tets, m.cluster, m.nclusters)
         ids = np.arange(m.nclusters, dtype=np.int32)
-        tk = ctx.submit(ids, 7)
+        g = ctx.graph_create(ids, 7)
+        tk = ctx.graph_launch(g)
+        ctx.poll(tk)
         st = ctx.stats()
         cf = pinlib.kuhn_counts(128)
         assert st["entries_built"] == 4 * m.nt + 2 * cf["E"] + (4 * m.nt - cf["Fb"])
-        rng = np.random.default_rng(123)
-        sample = sorted(set(rng.choice(m.nclusters, 48, replace=False).tolist()) | {0, m.nclusters - 1})
+        assert st["tt_exhaustive_blocks"] == 0
         orc = oracle.Oracle.of(m)
-        bad = []
-        tt_rows = 0
-        for k in range(m.nclusters):
-            rows, offs, ents = ctx.block(tk, k, 4)
-            tt_rows += len(rows)
-            if k in sample:
-                for rel in REL:
-                    got = ctx.block(tk, k, rel)
-                    exp = orc.block(k, rel)
-                    if not all(np.array_equal(g, e) for g, e in zip(got, exp)):
-                        bad.append((k, rel))
-        assert tt_rows == m.nt
-        assert ctx.stats()["tt_exhaustive_blocks"] == 0
+        bad = _compare_graph_blocks(ctx, tk, orc, range(m.nclusters))
         ctx.release(tk)
-        assert not bad, bad
+        ctx.graph_destroy(g)
+    assert not bad, bad[:10]
+
+
+def _sample_full_size(ctx, m, seed, frac=0.05, extremes=100):
+    """A seeded sample of at least `frac` of the clusters, the `extremes`
+    largest (vertices), the `extremes` with the longest VT row and the
+    `extremes` with the largest halo-to-star ratio, plus the first and last."""
+    rng = np.random.default_rng(seed)
+    ncl = m.nclusters
+    sizes = np.bincount(m.cluster, minlength=ncl)
+    import pandas as pd
+    deg = np.bincount(m.tets.ravel(), minlength=m.nv)
+    maxdeg = pd.Series(deg).groupby(m.cluster).max().reindex(range(ncl), fill_value=0).to_numpy()
+    info = [ctx.cluster_info(k) for k in range(ncl)]
+    ratio = np.array([i["nh"] / max(1, i["ns"]) for i in info])
+    nsamp = int(np.ceil(frac * ncl))
+    sample = set(rng.choice(ncl, nsamp, replace=False).tolist())
+    sample |= set(np.argsort(-sizes, kind="stable")[:extremes].tolist())
+    sample |= set(np.argsort(-maxdeg, kind="stable")[:extremes].tolist())
+    sample |= set(np.argsort(-ratio, kind="stable")[:extremes].tolist())
+    sample |= {0, ncl - 1}
+    return sorted(sample), int(maxdeg.max()), float(ratio.max())
+
+
+def _full_size_refined(cfg, seed):
+    """Config `cfg` built the way the benchmark builds it (autotuned launch
+    shapes, one graph replay of every cluster), compared with the oracle on
+    the sample of _sample_full_size."""
+    gale = _gale()
+    m = meshgen.config(cfg)
+    _say("config", cfg, "generated:", m.nv, "vertices", m.nt, "tetrahedra", m.nclusters, "clusters")
+    with gale.Context(form="batched") as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        _say("loaded in %.1f s" % ctx.stats()["load_seconds"])
+        ids = np.arange(m.nclusters, dtype=np.int32)
+        chosen, ms = ctx.autotune(ids, 7, reps=1)
+        _say("autotune", chosen, ms, "share", ctx.stats()["global_cu_share"])
+        g = ctx.graph_create(ids, 7)
+        tk = ctx.graph_launch(g)
+        ctx.poll(tk)
+        st = ctx.stats()
+        _say("built", st["entries_built"], "global-path blocks", st["global_path_blocks"],
+             "hybrid", st["hybrid_path_blocks"], "exhaustive", st["tt_exhaustive_blocks"])
+        assert st["tt_exhaustive_blocks"] == 0
+        sample, maxdeg, ratio = _sample_full_size(ctx, m, seed)
+        _say("sample", len(sample), "clusters; longest VT row", maxdeg, "largest halo/star %.3f" % ratio)
+        orc = oracle.Oracle.of(m)
+        _say("oracle ready")
+        bad = _compare_graph_blocks(ctx, tk, orc, sample)
+        ctx.release(tk)
+        ctx.graph_destroy(g)
+    assert not bad, bad[:10]
+    assert len(sample) >= 0.05 * m.nclusters
+
+
+def test_config3_sampled_full_size():
+    """The 256^3 lattice refined in Gaussian blobs (34M vertices, 151M
+    tetrahedra, 40,579 lognormal clusters of 64..8192 vertices)."""
+    _full_size_refined(3, 31)
+
+
+@pytest.mark.timeout(1500)
+def test_config5_sampled_full_size():
+    """The 384^3 lattice refined twice on 3 % of its tetrahedra (78M
+    vertices, 400M tetrahedra, 42,669 lognormal clusters, median 1024,
+    sigma 1.2)."""
+    _full_size_refined(5, 37)
 
 
 def test_alone_equals_batched_and_repeatable():
@@ -273,48 +351,6 @@ def test_hybrid_path_small_budgets(lds):
         st = ctx.stats()
         _say("global", st["global_path_blocks"], "hybrid", st["hybrid_path_blocks"])
         assert st["hybrid_path_blocks"] > 0
-
-
-def test_refined_256_full_size_sampled():
-    """The 256^3 lattice refined in Gaussian blobs (34M vertices, 151M
-    tetrahedra, 40,579 lognormal clusters of 64..8192 vertices) built the way
-    the benchmark times it: every cluster in one graph replay of the
-    persistent launches (workgroup shapes 1024/512/256 and the hybrid global
-    path on 65 % of the CUs, launched first).  A seeded sample of clusters,
-    the four largest and the first and last are read from that batch's device
-    blocks and compared with the oracle; no block needs the exhaustive TT
-    pairing and no cluster the all-global path."""
-    gale = _gale()
-    m = meshgen.config(3)
-    _say("256^3 refined", m.nv, m.nt, m.nclusters)
-    sizes = np.bincount(m.cluster, minlength=m.nclusters)
-    rng = np.random.default_rng(31)
-    sample = sorted(set(rng.choice(m.nclusters, 20, replace=False).tolist())
-                    | set(np.argsort(-sizes)[:4].tolist()) | {0, m.nclusters - 1})
-    with gale.Context(form="batched", launch_classes=6, global_cu_share=0.65) as ctx:
-        ctx.load(m.tets, m.cluster, m.nclusters)
-        _say("loaded")
-        g = ctx.graph_create(np.arange(m.nclusters, dtype=np.int32), 7)
-        tk = ctx.graph_launch(g)
-        ctx.poll(tk)
-        st = ctx.stats()
-        _say("built", st["entries_built"], "global-path blocks", st["global_path_blocks"],
-             "hybrid", st["hybrid_path_blocks"], "exhaustive", st["tt_exhaustive_blocks"])
-        assert st["tt_exhaustive_blocks"] == 0
-        assert st["global_path_blocks"] > 0 and st["hybrid_path_blocks"] == st["global_path_blocks"]
-        orc = oracle.Oracle.of(m)
-        _say("oracle ready")
-        bad = []
-        for k in sample:
-            for rel in REL:
-                v = ctx.block_device(tk, int(k), rel)
-                got = (_d2h(v.row_ids, v.nrows), _d2h(v.offsets, v.nrows + 1), _d2h(v.entries, v.nnz))
-                exp = orc.block(int(k), rel)
-                if not all(np.array_equal(a, b) for a, b in zip(got, exp)):
-                    bad.append((int(k), rel))
-        ctx.release(tk)
-        ctx.graph_destroy(g)
-    assert not bad, bad
 
 
 @pytest.mark.parametrize("classes", [7, 5])
@@ -486,4 +522,50 @@ def test_face_table_overflow_doubles_passes(path, lds):
             assert st["hybrid_path_blocks"] > 0
         else:
             assert st["global_path_blocks"] == 0
+        compare_all(ctx, m, orc)
+
+
+def test_graph_destroy_refused_while_a_ticket_lives():
+    """A graph's tickets borrow its buffers: gale_graph_destroy is refused
+    (ESTATE) until they are released, and works afterwards."""
+    gale = _gale()
+    m = SMALL["grid6"]
+    orc = oracle.Oracle.of(m)
+    ids = np.arange(m.nclusters, dtype=np.int32)
+    with gale.Context(form="batched") as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        g = ctx.graph_create(ids, 7)
+        tk = ctx.graph_launch(g)
+        with pytest.raises(gale.GaleError) as ei:
+            ctx.graph_destroy(g)
+        assert ei.value.status == gale.ESTATE
+        ctx.poll(tk)
+        for k in range(m.nclusters):
+            for rel in REL:
+                assert all(np.array_equal(a, b) for a, b in zip(_device_block(ctx, tk, k, rel), orc.block(k, rel)))
+        ctx.release(tk)
+        ctx.graph_destroy(g)
+
+
+def test_tune_table_written_and_applied(tmp_path):
+    """gale_autotune writes its choice to the tune table; a new context on
+    the same mesh applies it at load and builds the same blocks."""
+    import json
+    gale = _gale()
+    m, orc = _refined36()
+    path = str(tmp_path / "tune.json")
+    ids = np.arange(m.nclusters, dtype=np.int32)
+    with gale.Context(form="batched", tune_table_path=path) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        assert ctx.stats()["tune_applied"] == 0
+        chosen, _ = ctx.autotune(ids, 7, reps=1)
+        share = ctx.stats()["global_cu_share"]
+    t = json.load(open(path))
+    ent = [e for e in t["entries"] if e["nv"] == m.nv and e["nt"] == m.nt]
+    assert len(ent) == 1 and ent[0]["launch_classes"] == chosen
+    assert abs(ent[0]["global_cu_share"] - share) < 1e-3
+    with gale.Context(form="batched", tune_table_path=path) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        st = ctx.stats()
+        assert st["tune_applied"] == 1 and abs(st["global_cu_share"] - share) < 1e-3
         compare_all(ctx, m, orc)

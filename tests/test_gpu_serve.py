@@ -222,3 +222,230 @@ def test_native_consumers_count_like_the_oracle(mode):
     assert res["mismatches"] == 0
     assert res["clusters"] == m.nclusters
     assert [res["regular"], res["minima"], res["maxima"], res["saddles"]] == tot.tolist()
+
+
+def _block_bytes(info, mask):
+    """Bytes the serving cache reserves for a block of this cluster before it
+    is built: the block layout with the default capacities (exact VT, 4 TT
+    entries per row, the VV bound), each array on a 32-word boundary."""
+    al = lambda w: (w + 31) // 32 * 32
+    nV, nT, nvt, cvv = info["nV"], info["nT"], info["nnzVT"], info["cap_vv"]
+    w = al(8)
+    if mask & 3:
+        w = al(w + nV)
+    if mask & 1:
+        w = al(w + nV + 1)
+        w = al(w + nvt)
+    if mask & 4:
+        w = al(w + nT)
+        w = al(w + nT + 1)
+        w = al(w + 4 * nT)
+    if mask & 2:
+        w = al(w + nV + 1)
+        w = al(w + cvv)
+    return (4 * w + 255) // 256 * 256
+
+
+def test_prefetch_blocks_equal_oracle_and_are_evicted_first():
+    """Speculative builds of the clusters following a request (the leader's
+    proactive precomputation, prefetch_depth 2): a later request for one of
+    them is a hit on a block equal to the oracle's, and when space runs out
+    speculative blocks are evicted before the block a request used."""
+    gale = _gale()
+    m = meshgen.grid_mesh(20, 100, seed=3)
+    orc = oracle.Oracle.of(m)
+    with gale.Context(mode="direct") as probe:
+        probe.load(m.tets, m.cluster, m.nclusters)
+        info = {k: probe.cluster_info(k) for k in range(m.nclusters)}
+    need = _block_bytes(info[10], 7) + _block_bytes(info[50], 7) + \
+        max(_block_bytes(info[11], 7), _block_bytes(info[12], 7))
+    with gale.Context(mode="serve", cache_budget_bytes=need + 256, max_inflight=2, prefetch_depth=2) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        tk = ctx.submit([10], 7)
+        ctx.poll(tk)
+        ctx.release(tk)
+        st = ctx.stats()
+        _say("after 10", {k: st[k] for k in ("prefetch_built", "prefetch_hits", "evictions", "cache_misses")})
+        assert st["prefetch_built"] >= 1
+        # cluster 11 was built ahead of this request
+        tk = ctx.submit([11], 7)
+        ctx.poll(tk)
+        for rel in REL:
+            assert all(np.array_equal(g, e) for g, e in zip(ctx.block(tk, 11, rel), orc.block(11, rel)))
+        ctx.release(tk)
+        st = ctx.stats()
+        assert st["prefetch_hits"] >= 1 and st["cache_misses"] == 1
+        # a far cluster needs space: speculative blocks go, the used ones stay
+        tk = ctx.submit([50], 7)
+        ctx.poll(tk)
+        for rel in REL:
+            assert all(np.array_equal(g, e) for g, e in zip(ctx.block(tk, 50, rel), orc.block(50, rel)))
+        ctx.release(tk)
+        st = ctx.stats()
+        _say("after 50", {k: st[k] for k in ("prefetch_built", "prefetch_evicted", "demand_evictions", "evictions")})
+        assert st["prefetch_evicted"] >= 1
+        before = st["cache_misses"]
+        tk = ctx.submit([10], 7)
+        ctx.poll(tk)
+        for rel in REL:
+            assert all(np.array_equal(g, e) for g, e in zip(ctx.block(tk, 10, rel), orc.block(10, rel)))
+        ctx.release(tk)
+        assert ctx.stats()["cache_misses"] == before  # still resident
+
+
+@pytest.mark.parametrize("budget_mb", [256, 1])
+def test_per_relation_front_end_matches_oracle(budget_mb):
+    """The per-relation front end (one queue and one leader thread per
+    relation, each request split into one part per relation): 16 threads
+    with mixed masks, every block equal to the oracle's; a 1 MiB budget
+    forces evictions."""
+    gale = _gale()
+    m = meshgen.grid_mesh(20, 100, seed=3)
+    orc = oracle.Oracle.of(m)
+    exp = _expected(orc, m.nclusters, 7)
+    rng = np.random.default_rng(9)
+    masks = [7, 3, 1, 2, 4, 6, 5]
+    with gale.Context(mode="serve", cache_budget_bytes=budget_mb << 20, max_inflight=2,
+                      front_end="per_relation") as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        assert ctx.stats()["front_end"] == gale.FRONT_PER_RELATION
+        errors = []
+
+        def worker(t):
+            r = np.random.default_rng(100 + t)
+            for i in range(10):
+                mask = masks[(t + i) % len(masks)]
+                ids = r.choice(m.nclusters, size=1 + (i % 3), replace=False).astype(np.int32)
+                _consumer(ctx, [ids], mask, exp, errors, t)
+        th = [threading.Thread(target=worker, args=(t,)) for t in range(16)]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        assert not errors, errors[:10]
+        st = ctx.stats()
+        _say("per-relation", {k: st[k] for k in ("cache_hits", "cache_misses", "evictions", "batches",
+                                                 "lat_p50_us", "lat_p99_us", "queue_depth_mean")})
+        assert st["lat_count"] == 160
+        if budget_mb == 1:
+            assert st["evictions"] > 0
+
+
+def test_per_relation_native_consumers():
+    gale = _gale()
+    m = meshgen.grid_mesh(16, 64, seed=8)
+    field = meshgen.gauss_field(m.coords.astype(np.float64), 16, np.random.default_rng(4))
+    orc = oracle.Oracle.of(m)
+    tot = np.zeros(4, np.int64)
+    for k in range(m.nclusters):
+        vt, vv = orc.block(k, 1), orc.block(k, 2)
+        tot += np.bincount(gale.lowerstar_classify(vt[0], vt, vv, m.tets, field), minlength=4)
+    with gale.Context(mode="serve", cache_budget_bytes=256 << 10, max_inflight=2, front_end="per_relation") as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        res = gale.consumer_run(ctx, m.tets, field, np.arange(m.nclusters), threads=24, seed=5)
+        st = ctx.stats()
+    _say("per-relation native", {k: res[k] for k in ("accesses", "mismatches", "errors", "lat_p50_us")},
+         {k: st[k] for k in ("stage_push_us", "stage_queue_us", "stage_prep_us", "stage_kernel_copy_us",
+                              "wait_queue_s_max")})
+    assert res["errors"] == 0 and res["mismatches"] == 0
+    assert [res["regular"], res["minima"], res["maxima"], res["saddles"]] == tot.tolist()
+
+
+def test_borrowed_arena_from_torch():
+    """The HBM cache in device memory the caller owns (a torch tensor)."""
+    import torch
+    gale = _gale()
+    torch.cuda.set_device(0)
+    arena = torch.empty(8 << 20, dtype=torch.uint8, device="cuda")
+    m = meshgen.grid_mesh(12, 100, seed=5)
+    orc = oracle.Oracle.of(m)
+    exp = _expected(orc, m.nclusters, 7)
+    with gale.Context(mode="serve", dev_arena=arena.data_ptr(), arena_bytes=arena.numel(),
+                      cache_budget_bytes=4 << 20) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        assert ctx.stats()["cache_budget"] == 4 << 20
+        errors = []
+        _consumer(ctx, [np.array([k], np.int32) for k in range(m.nclusters)], 7, exp, errors, 0)
+        assert not errors, errors[:5]
+    with pytest.raises(gale.GaleError) as ei:
+        gale.Context(mode="direct", dev_arena=arena.data_ptr(), arena_bytes=arena.numel())
+    assert ei.value.status == gale.EINVAL
+    del arena
+
+
+def test_stage_breakdown_and_queue_depth():
+    """The paper's five waiting stages and the queue depth at admission are
+    reported, consistent with the total latency."""
+    gale = _gale()
+    m = meshgen.grid_mesh(16, 64, seed=8)
+    field = meshgen.gauss_field(m.coords.astype(np.float64), 16, np.random.default_rng(4))
+    with gale.Context(mode="serve", cache_budget_bytes=1 << 20, max_inflight=3) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        res = gale.consumer_run(ctx, m.tets, field, np.arange(m.nclusters), threads=16, seed=2)
+        st = ctx.stats()
+    parts = st["stage_push_us"] + (st["stage_queue_us"] - st["stage_push_us"]) + st["stage_prep_us"] + \
+        st["stage_kernel_copy_us"] + st["stage_integration_us"]
+    _say("stages", {k: round(st[k], 1) for k in st if k.startswith("stage_")}, "mean", st["lat_mean_us"],
+         "depth", st["queue_depth_mean"], st["queue_depth_max"])
+    assert res["errors"] == 0
+    assert abs(parts - st["lat_mean_us"]) <= 0.02 * st["lat_mean_us"] + 1.0
+    assert st["queue_depth_max"] >= 1 and st["queue_depth_mean"] >= 1.0
+    assert st["wait_queue_s_max"] > 0 and st["wait_kernel_copy_s_max"] > 0
+
+
+@pytest.mark.timeout(900)
+def test_config4_served_blocks_with_evictions():
+    """The config-4 mesh (the refined 256^3 mesh with its scalar field)
+    served with the 4 GB cache budget: 40 native consumer threads walk
+    24,000 clusters in Morton order with Zipf re-access (more block bytes
+    than the budget holds, so blocks are evicted) while four Python threads
+    request a seeded sample of the same clusters in the mix; every sampled
+    block equals the oracle's and no consumer label changes."""
+    gale = _gale()
+    m = meshgen.config(4)
+    _say("config 4", m.nv, m.nt, m.nclusters)
+    orc = oracle.Oracle.of(m)
+    ncur = 24000
+    rng = np.random.default_rng(41)
+    sample = np.sort(rng.choice(ncur, 1200, replace=False)).astype(np.int32)
+    with gale.Context(mode="serve", cache_budget_bytes=4 << 30, max_inflight=4) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        _say("loaded")
+        errors, done = [], []
+
+        def sampler(t):
+            part = sample[t::4]
+            for c0 in range(0, len(part), 50):
+                ids = part[c0:c0 + 50]
+                exp = orc.blocks([(int(k), rel) for k in ids for rel in REL], threads=4)
+                i = 0
+                for k in ids:
+                    try:
+                        tk = ctx.submit([int(k)], 7)
+                        ctx.poll(tk)
+                        for rel in REL:
+                            got = ctx.block(tk, int(k), rel)
+                            if not all(np.array_equal(g, x) for g, x in zip(got, exp[i])):
+                                errors.append((int(k), rel))
+                            i += 1
+                        ctx.release(tk)
+                    except Exception as ex:
+                        errors.append((int(k), repr(ex)))
+                        return
+            done.append(t)
+        th = [threading.Thread(target=sampler, args=(t,)) for t in range(4)]
+        for x in th:
+            x.start()
+        res = gale.consumer_run(ctx, m.tets, m.scalar, np.arange(ncur, dtype=np.int32), threads=40, seed=0)
+        _say("consumers", {k: res[k] for k in ("accesses", "reaccesses", "mismatches", "errors", "lat_p50_us",
+                                               "lat_p99_us")})
+        for x in th:
+            x.join()
+        st = ctx.stats()
+        _say("cache", {k: st[k] for k in ("cache_hits", "cache_misses", "evictions", "cache_bytes_resident",
+                                          "cache_budget", "queue_depth_mean", "tt_exhaustive_blocks")})
+    assert not errors, errors[:10]
+    assert len(done) == 4
+    assert res["errors"] == 0 and res["mismatches"] == 0
+    assert st["evictions"] > 0
+    assert st["tt_exhaustive_blocks"] == 0
