@@ -86,18 +86,16 @@ def kuhn_grid(n: int):
     k, j, i = np.meshgrid(ax, ax, ax, indexing="ij")
     coords = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1)
     m = n - 1
-    it = np.int64 if n ** 3 >= 2 ** 31 else np.int32
-    c = np.arange(m, dtype=it)
-    ck, cj, ci = np.meshgrid(c, c, c, indexing="ij")
-    p0 = (ci + n * (cj + n * ck)).ravel()
+    if n ** 3 >= 2 ** 31:
+        raise ValueError("n^3 must stay below 2^31 (int32 vertex ids)")
+    c = np.arange(m, dtype=np.int64)
+    p0 = (c[None, None, :] + n * (c[None, :, None] + n * c[:, None, None])).ravel().astype(np.int32)
     step = (1, n, n * n)
-    tets = np.empty((p0.shape[0], 6, 4), dtype=it)
+    off = np.empty((6, 4), dtype=np.int32)
     for o, (a, b, _c) in enumerate(_AXIS_ORDERS):
-        tets[:, o, 0] = p0
-        tets[:, o, 1] = p0 + step[a]
-        tets[:, o, 2] = p0 + step[a] + step[b]
-        tets[:, o, 3] = p0 + 1 + n + n * n
-    return coords, tets.reshape(-1, 4).astype(np.int32)
+        off[o] = (0, step[a], step[a] + step[b], 1 + n + n * n)
+    tets = (p0[:, None, None] + off[None, :, :]).reshape(-1, 4)
+    return coords, tets
 
 
 # ----------------------------------------------------------------------------

@@ -192,15 +192,23 @@ gale_status prepare_streams(int32_t nv, int64_t nt, const int32_t *tv, const int
     cnt.clear();
     cnt.shrink_to_fit();
 
-    // 4. halo.  Global VT (lists ascending) for the triangles that need it.
+    // 4. halo.  Global VT (lists ascending) for the triangles that need it:
+    // counts by atomic increments, then each list filled and sorted.
     std::vector<int64_t> vtoff(nv + 1, 0);
-    for (int64_t i = 0; i < 4 * nt; ++i) vtoff[tv[i] + 1]++;
+    parallel_for(nt, [&](int64_t b, int64_t e, int) {
+        for (int64_t i = 4 * b; i < 4 * e; ++i) __atomic_fetch_add(&vtoff[tv[i] + 1], 1, __ATOMIC_RELAXED);
+    });
     for (int32_t v = 0; v < nv; ++v) vtoff[v + 1] += vtoff[v];
     std::vector<int32_t> vt(4 * nt);
     {
         std::vector<int64_t> f(vtoff.begin(), vtoff.end() - 1);
-        for (int64_t t = 0; t < nt; ++t)
-            for (int i = 0; i < 4; ++i) vt[f[tv[4 * t + i]]++] = (int32_t)t;
+        parallel_for(nt, [&](int64_t b, int64_t e, int) {
+            for (int64_t t = b; t < e; ++t)
+                for (int i = 0; i < 4; ++i) vt[__atomic_fetch_add(&f[tv[4 * t + i]], 1, __ATOMIC_RELAXED)] = (int32_t)t;
+        });
+        parallel_for(nv, [&](int64_t b, int64_t e, int) {
+            for (int64_t v = b; v < e; ++v) std::sort(vt.begin() + vtoff[v], vt.begin() + vtoff[v + 1]);
+        });
     }
     std::vector<std::vector<std::pair<int32_t, int32_t>>> halo_parts(P);
     {
@@ -268,15 +276,25 @@ gale_status prepare_streams(int32_t nv, int64_t nt, const int32_t *tv, const int
     for (auto &p : halo) hoff[p.first + 1]++;
     for (int32_t k = 0; k < ncl; ++k) hoff[k + 1] += hoff[k];
 
-    // 5. local tables and encoded streams, per cluster
+    // 5. local tables and encoded streams, per cluster.  Each thread keeps
+    // two arrays over all vertices: the last cluster that met the vertex
+    // (distinct vertices without sorting the star's four-per-tetrahedron
+    // list) and the vertex's local id in the cluster it works on.
     out.meta.assign(ncl, ClusterMeta{});
     std::vector<std::vector<int32_t>> ltab(ncl);
     std::atomic<int32_t> next{0};
     std::atomic<int> too_big{0};
+    // row index of every vertex within its cluster (rank by ascending id)
+    std::vector<int32_t> rowof(nv);
+    parallel_for(ncl, [&](int64_t b, int64_t e, int) {
+        for (int64_t k = b; k < e; ++k)
+            for (int64_t s2 = voff[k]; s2 < voff[k + 1]; ++s2) rowof[vrows[s2]] = (int32_t)(s2 - voff[k]);
+    });
     {
         std::vector<std::thread> th;
         for (int i = 0; i < P; ++i) {
             th.emplace_back([&] {
+                std::vector<int32_t> stamp(nv, -1);
                 std::vector<int32_t> deg;
                 while (true) {
                     const int32_t k = next.fetch_add(1);
@@ -285,14 +303,19 @@ gale_status prepare_streams(int32_t nv, int64_t nt, const int32_t *tv, const int
                     const int64_t s0 = soff[k], s1 = soff[k + 1];
                     const int64_t h0 = hoff[k], h1 = hoff[k + 1];
                     tab.clear();
-                    tab.reserve((size_t)(4 * (s1 - s0 + h1 - h0) + voff[k + 1] - voff[k]));
-                    for (int64_t s = s0; s < s1; ++s)
-                        for (int j = 0; j < 4; ++j) tab.push_back(tv[4 * (int64_t)star[s] + j]);
-                    for (int64_t s = h0; s < h1; ++s)
-                        for (int j = 0; j < 4; ++j) tab.push_back(tv[4 * (int64_t)halo[s].second + j]);
-                    for (int64_t s = voff[k]; s < voff[k + 1]; ++s) tab.push_back(vrows[s]);
+                    auto add = [&](int32_t v) {
+                        if (stamp[v] != k) {
+                            stamp[v] = k;
+                            tab.push_back(v);
+                        }
+                    };
+                    for (int64_t s2 = s0; s2 < s1; ++s2)
+                        for (int j = 0; j < 4; ++j) add(tv[4 * (int64_t)star[s2] + j]);
+                    for (int64_t s2 = h0; s2 < h1; ++s2)
+                        for (int j = 0; j < 4; ++j) add(tv[4 * (int64_t)halo[s2].second + j]);
+                    for (int64_t s2 = voff[k]; s2 < voff[k + 1]; ++s2) add(vrows[s2]);
                     std::sort(tab.begin(), tab.end());
-                    tab.erase(std::unique(tab.begin(), tab.end()), tab.end());
+                    tab.shrink_to_fit();
                     ClusterMeta &m = out.meta[k];
                     m.ns = (int32_t)(s1 - s0);
                     m.nh = (int32_t)(h1 - h0);
@@ -301,17 +324,14 @@ gale_status prepare_streams(int32_t nv, int64_t nt, const int32_t *tv, const int
                     if ((int64_t)tab.size() > 0x7fffffffLL) too_big = 1;
                     int64_t nnz = 0, nT = 0;
                     deg.assign(m.nV, 0);
-                    for (int64_t s = s0; s < s1; ++s) {
-                        const int32_t t = star[s];
+                    for (int64_t s2 = s0; s2 < s1; ++s2) {
+                        const int32_t t = star[s2];
                         if (owner[t] == k) ++nT;
                         for (int j = 0; j < 4; ++j) {
                             const int32_t v = tv[4 * (int64_t)t + j];
                             if (cl[v] == k) {
                                 ++nnz;
-                                // row index = rank of v among C's vertices (ascending id)
-                                const int32_t *rb = vrows.data() + voff[k];
-                                const int64_t r = std::lower_bound(rb, rb + m.nV, v) - rb;
-                                deg[r]++;
+                                deg[rowof[v]]++;
                             }
                         }
                     }
@@ -356,20 +376,20 @@ gale_status prepare_streams(int32_t nv, int64_t nt, const int32_t *tv, const int
         std::vector<std::thread> th;
         for (int i = 0; i < P; ++i) {
             th.emplace_back([&] {
+                std::vector<int32_t> lid(nv, 0);  // local id of a vertex in the current cluster
                 while (true) {
                     const int32_t k = next.fetch_add(1);
                     if (k >= ncl) break;
                     const auto &tab = ltab[k];
                     const ClusterMeta &m = out.meta[k];
+                    for (int32_t l = 0; l < m.L; ++l) lid[tab[l]] = l;
                     for (int32_t l = 0; l < m.L; ++l) {
                         const int32_t v = tab[l];
                         const uint32_t row = cl[v] == k ? 0x80000000u : 0u;
                         const uint32_t lower = cl[v] < k ? 0x40000000u : 0u;
                         out.lverts[m.lv_off + l] = (int32_t)((uint32_t)v | row | lower);
                     }
-                    auto local = [&](int32_t v) -> int32_t {
-                        return (int32_t)(std::lower_bound(tab.begin(), tab.end(), v) - tab.begin());
-                    };
+                    auto local = [&](int32_t v) -> int32_t { return lid[v]; };
                     const bool wide = (m.flags & kMetaWide) != 0;
                     uint8_t *tb = out.tets.data() + m.tb_off;
                     auto put = [&](int64_t i, int32_t t) {

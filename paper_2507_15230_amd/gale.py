@@ -105,6 +105,15 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError("libgale.so is not built (%s); run __graft_entry__.build()" % path)
+    # PyTorch ships its own HIP runtime under the same sonames as the system
+    # one this library links to.  Loading torch first makes the library's
+    # dependency resolve to the runtime already in the process, so the
+    # library and torch (device memory, streams) share one runtime whatever
+    # order the caller initialises them in.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     i32p = C.POINTER(C.c_int32)
     vp = C.c_void_p
