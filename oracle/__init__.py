@@ -7,7 +7,9 @@ paper (Section 2.2, Table 1; Section 4.3 for the internal/external rule); it
 shares no code with the GPU path.
 
 Functions pinned against the paper and the mathematics by
-``tests/test_oracle_pins.py``: VT, VV and TT blocks and the owner rule.
+``tests/test_oracle_pins.py``: VT, VV and TT blocks and the owner rule; by
+``tests/test_oracle_simplices.py``: the edge and triangle lists E, F with their
+interval arrays, and the VE, VF, EF, ET and FT blocks.
 """
 from __future__ import annotations
 
@@ -22,6 +24,8 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 REL_VT, REL_VV, REL_TT = 1, 2, 4
+REL_VE, REL_VF, REL_EF, REL_ET, REL_FT = 8, 16, 32, 64, 128
+_COBOUND = REL_VE | REL_VF | REL_EF | REL_ET | REL_FT
 _lib = None
 
 
@@ -68,6 +72,15 @@ def _load():
     lib.oracle_block_into.restype = C.c_int
     lib.oracle_buf_copy.argtypes = [C.c_void_p, i32p, i32p, i32p]
     lib.oracle_buf_copy.restype = None
+    lib.oracle_enumerate.argtypes = [C.c_void_p]
+    lib.oracle_enumerate.restype = C.c_int
+    lib.oracle_num_edges.argtypes = [C.c_void_p]
+    lib.oracle_num_edges.restype = C.c_int64
+    lib.oracle_num_faces.argtypes = [C.c_void_p]
+    lib.oracle_num_faces.restype = C.c_int64
+    i64p = C.POINTER(C.c_int64)
+    lib.oracle_simplices.argtypes = [C.c_void_p, i32p, i64p, i32p, i64p]
+    lib.oracle_simplices.restype = None
     _lib = lib
     return lib
 
@@ -118,7 +131,30 @@ class Oracle:
     def set_mutation(self, m: int):
         self._lib.oracle_set_mutation(self._h, int(m))
 
+    def enumerate(self):
+        """Number the edges and triangles (Section 4.3, read through the
+        example of Section 4.4); needed by the VE / VF / EF / ET / FT blocks."""
+        st = self._lib.oracle_enumerate(self._h)
+        if st != 0:
+            raise MemoryError("oracle_enumerate failed with status %d" % st)
+
+    def simplices(self):
+        """(E as ne x 2, I_E as ncl + 1, F as nf x 3, I_F as ncl + 1)."""
+        self.enumerate()
+        ne = int(self._lib.oracle_num_edges(self._h))
+        nf = int(self._lib.oracle_num_faces(self._h))
+        e = np.empty((ne, 2), np.int32)
+        f = np.empty((nf, 3), np.int32)
+        ie = np.empty(self.nclusters + 1, np.int64)
+        if_ = np.empty(self.nclusters + 1, np.int64)
+        i32p, i64p = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+        self._lib.oracle_simplices(self._h, e.ctypes.data_as(i32p), ie.ctypes.data_as(i64p),
+                                   f.ctypes.data_as(i32p), if_.ctypes.data_as(i64p))
+        return e, ie, f, if_
+
     def block(self, k: int, rel: int):
+        if rel & _COBOUND:
+            self.enumerate()
         nr = C.c_int64()
         nz = C.c_int64()
         st = self._lib.oracle_block(self._h, int(k), int(rel), C.byref(nr), C.byref(nz))
@@ -140,6 +176,8 @@ class Oracle:
         import threading
         from concurrent.futures import ThreadPoolExecutor
         pairs = list(pairs)
+        if any(r & _COBOUND for _, r in pairs):
+            self.enumerate()
         threads = threads or min(16, os.cpu_count() or 1)
         local = threading.local()
         bufs = []

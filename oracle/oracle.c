@@ -32,6 +32,24 @@
  *   O3 TT rows per cluster by the owner rule; O4 emit (row ids, offsets from 0,
  *   entries) in original ids.
  *
+ * Edges and triangles (oracle_enumerate; Section 4.3 "Initialization", read
+ * through the worked example of Section 4.4): the lists E and F number every
+ * edge and triangle of the mesh, each stored as its ascending vertex tuple.
+ * For each cluster k in turn, the cluster's tetrahedra (those with a vertex
+ * in k) are visited in ascending id; each tetrahedron's edges (triangles) are
+ * taken as the pairs (triples) of its ascending vertices in lexicographic
+ * order, and an edge internal to k (smallest cluster among its vertices = k)
+ * that is not listed yet is appended.  I_E[k] is the first id of cluster k's
+ * edges (the interval array of Section 4.3).  With this order the example of
+ * Section 4.4 comes out as printed (12 edges, I_E = 0, 9, 12; f5 = v0 v3 v4 and
+ * FE(f5) = e2, e6, e9), which a plain lexicographic sort would not give.
+ * The further coboundary relations (Section 2.2, Table 1) per cluster k:
+ *   - VE(v), VF(v): ids of the edges / triangles containing v, rows = the
+ *     vertices of k;
+ *   - EF(e), ET(e): ids of the triangles / tetrahedra containing e, rows = the
+ *     edges internal to k in id order (row ids are edge ids);
+ *   - FT(f): the tetrahedra containing f, rows = the triangles internal to k.
+ *
  * Planted mistakes: oracle_set_mutation() switches on one deliberately wrong
  * variant so the tests can show that their pins catch it.  Mutation 0 (the
  * default) is the oracle proper.
@@ -47,6 +65,11 @@
 #define REL_VT 1
 #define REL_VV 2
 #define REL_TT 4
+#define REL_VE 8
+#define REL_VF 16
+#define REL_EF 32
+#define REL_ET 64
+#define REL_FT 128
 
 /* One block's arrays (rows, offsets, entries) and their capacities.  A
  * context is read-only while blocks are built, so threads that each own a
@@ -73,6 +96,18 @@ typedef struct {
     int mutation;
     int owner_mut;      /* mutation the owner table was built under */
     oracle_buf b;       /* the block last built by oracle_block */
+    /* edges and triangles (oracle_enumerate): E[i] = (ea[i], eb[i]) with
+     * ea < eb, F[i] = (fa, fb, fc) ascending; cluster k's internal ones are
+     * ids [ie[k], ie[k+1]) and [if_[k], if_[k+1]).  Lookup lists: for each
+     * vertex a, the edges / triangles whose smallest vertex is a, with ids. */
+    int enumerated;
+    int64_t ne, nf;
+    int32_t *ea, *eb, *fa, *fb, *fc;
+    int64_t *ie, *if_;
+    int64_t *el_off, *fl_off;  /* nv+1: list capacity of each vertex */
+    int32_t *el_n, *fl_n;      /* nv: list length */
+    int32_t *el_b, *fl_b, *fl_c;
+    int64_t *el_id, *fl_id;
 } oracle_ctx;
 
 static int cmp_i32(const void *a, const void *b) {
@@ -95,6 +130,9 @@ void oracle_destroy(oracle_ctx *c) {
     free(c->tv); free(c->cl); free(c->vt_off); free(c->vt); free(c->owner);
     free(c->vrow_off); free(c->vrows); free(c->trow_off); free(c->trows);
     free(c->b.rows); free(c->b.off); free(c->b.ent);
+    free(c->ea); free(c->eb); free(c->fa); free(c->fb); free(c->fc); free(c->ie); free(c->if_);
+    free(c->el_off); free(c->fl_off); free(c->el_n); free(c->fl_n); free(c->el_b); free(c->fl_b);
+    free(c->fl_c); free(c->el_id); free(c->fl_id);
     free(c);
 }
 
@@ -207,6 +245,285 @@ static void refresh_rows(oracle_ctx *c) {
     c->owner_mut = c->mutation;
 }
 
+/* ---------------------------------------------------------------------------
+ * Edges and triangles
+ * ------------------------------------------------------------------------ */
+
+/* owner of a simplex: the smallest cluster id among its n vertices (the
+ * largest under planted mistake 3) */
+static int32_t simplex_owner(const oracle_ctx *c, const int32_t *q, int n) {
+    int32_t o = c->cl[q[0]];
+    for (int i = 1; i < n; ++i) {
+        int32_t k = c->cl[q[i]];
+        if (c->mutation == 3 ? (k > o) : (k < o)) o = k;
+    }
+    return o;
+}
+
+/* id of edge {a < b}, or -1 */
+static int64_t edge_id(const oracle_ctx *c, int32_t a, int32_t b) {
+    const int64_t o = c->el_off[a];
+    for (int32_t i = 0; i < c->el_n[a]; ++i)
+        if (c->el_b[o + i] == b) return c->el_id[o + i];
+    return -1;
+}
+
+/* id of triangle {a < b < c3}, or -1 */
+static int64_t face_id(const oracle_ctx *c, int32_t a, int32_t b, int32_t c3) {
+    const int64_t o = c->fl_off[a];
+    for (int32_t i = 0; i < c->fl_n[a]; ++i)
+        if (c->fl_b[o + i] == b && c->fl_c[o + i] == c3) return c->fl_id[o + i];
+    return -1;
+}
+
+static void sort4(int32_t *q) {
+    for (int i = 1; i < 4; ++i)
+        for (int j = i; j > 0 && q[j - 1] > q[j]; --j) {
+            int32_t x = q[j]; q[j] = q[j - 1]; q[j - 1] = x;
+        }
+}
+
+/* the tetrahedra with a vertex in cluster k, ascending id; returns the count
+ * (out holds at least the sum of the rows' VT degrees) */
+static int64_t star_of(const oracle_ctx *c, int32_t k, int32_t *out) {
+    int64_t n = 0;
+    for (int64_t r = c->vrow_off[k]; r < c->vrow_off[k + 1]; ++r) {
+        int32_t v = c->vrows[r];
+        for (int64_t i = c->vt_off[v]; i < c->vt_off[v + 1]; ++i) out[n++] = c->vt[i];
+    }
+    return sort_unique(out, n);
+}
+
+/* planted mistake 10: a cluster's edges and triangles in ascending vertex
+ * tuples instead of discovery order (ids in the lookup lists rewritten) */
+static int cmp_pair(const void *x, const void *y) {
+    const int64_t *p = (const int64_t *)x, *q = (const int64_t *)y;
+    return (p[0] > q[0]) - (p[0] < q[0]);
+}
+static void relist_sorted(oracle_ctx *c, int64_t e0, int64_t e1, int64_t f0, int64_t f1) {
+    int64_t n = e1 - e0 > f1 - f0 ? e1 - e0 : f1 - f0;
+    int64_t *key = (int64_t *)malloc(sizeof(int64_t) * 2 * (size_t)(n + 1));
+    int32_t *t0 = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)(n + 1));
+    for (int64_t i = e0; i < e1; ++i) {
+        key[2 * (i - e0)] = ((int64_t)c->ea[i] << 31) | c->eb[i];
+        key[2 * (i - e0) + 1] = i;
+    }
+    qsort(key, (size_t)(e1 - e0), 2 * sizeof(int64_t), cmp_pair);
+    for (int64_t i = 0; i < e1 - e0; ++i) { t0[2 * i] = c->ea[key[2 * i + 1]]; t0[2 * i + 1] = c->eb[key[2 * i + 1]]; }
+    for (int64_t i = 0; i < e1 - e0; ++i) {
+        c->ea[e0 + i] = t0[2 * i]; c->eb[e0 + i] = t0[2 * i + 1];
+        const int64_t o = c->el_off[c->ea[e0 + i]];
+        for (int32_t j = 0; j < c->el_n[c->ea[e0 + i]]; ++j)
+            if (c->el_b[o + j] == c->eb[e0 + i]) c->el_id[o + j] = e0 + i;
+    }
+    (void)f0; (void)f1;
+    free(key); free(t0);
+}
+
+/* Number the edges and triangles (see the header).  Idempotent. */
+int oracle_enumerate(oracle_ctx *c) {
+    if (c->enumerated) return ORC_OK;
+    const int32_t nv = c->nv, ncl = c->ncl;
+    const int64_t nt = c->nt;
+    c->el_off = (int64_t *)calloc((size_t)nv + 1, sizeof(int64_t));
+    c->fl_off = (int64_t *)calloc((size_t)nv + 1, sizeof(int64_t));
+    c->el_n = (int32_t *)calloc((size_t)nv + 1, sizeof(int32_t));
+    c->fl_n = (int32_t *)calloc((size_t)nv + 1, sizeof(int32_t));
+    c->ie = (int64_t *)calloc((size_t)ncl + 1, sizeof(int64_t));
+    c->if_ = (int64_t *)calloc((size_t)ncl + 1, sizeof(int64_t));
+    if (!c->el_off || !c->fl_off || !c->el_n || !c->fl_n || !c->ie || !c->if_) return ORC_ENOMEM;
+    /* a tetrahedron containing a has at most three edges and three triangles
+     * whose smallest vertex is a */
+    for (int32_t v = 0; v < nv; ++v) {
+        const int64_t d = c->vt_off[v + 1] - c->vt_off[v];
+        c->el_off[v + 1] = c->el_off[v] + 3 * d;
+        c->fl_off[v + 1] = c->fl_off[v] + 3 * d;
+    }
+    const size_t cap = (size_t)c->el_off[nv] + 1;
+    c->el_b = (int32_t *)malloc(sizeof(int32_t) * cap);
+    c->el_id = (int64_t *)malloc(sizeof(int64_t) * cap);
+    c->fl_b = (int32_t *)malloc(sizeof(int32_t) * cap);
+    c->fl_c = (int32_t *)malloc(sizeof(int32_t) * cap);
+    c->fl_id = (int64_t *)malloc(sizeof(int64_t) * cap);
+    c->ea = (int32_t *)malloc(sizeof(int32_t) * (size_t)(6 * nt + 1));
+    c->eb = (int32_t *)malloc(sizeof(int32_t) * (size_t)(6 * nt + 1));
+    c->fa = (int32_t *)malloc(sizeof(int32_t) * (size_t)(4 * nt + 1));
+    c->fb = (int32_t *)malloc(sizeof(int32_t) * (size_t)(4 * nt + 1));
+    c->fc = (int32_t *)malloc(sizeof(int32_t) * (size_t)(4 * nt + 1));
+    int32_t *star = (int32_t *)malloc(sizeof(int32_t) * (size_t)(4 * nt + 1));
+    if (!c->el_b || !c->el_id || !c->fl_b || !c->fl_c || !c->fl_id || !c->ea || !c->eb || !c->fa || !c->fb ||
+        !c->fc || !star) {
+        free(star);
+        return ORC_ENOMEM;
+    }
+    static const int P2[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    static const int P3[4][3] = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
+    int64_t ne = 0, nf = 0;
+    for (int32_t k = 0; k < ncl; ++k) {
+        c->ie[k] = ne;
+        c->if_[k] = nf;
+        const int64_t ns = star_of(c, k, star);
+        for (int64_t i = 0; i < ns; ++i) {
+            int32_t s[4];
+            memcpy(s, c->tv + 4 * (int64_t)star[i], sizeof(s));
+            sort4(s);
+            for (int j = 0; j < 6; ++j) {
+                int32_t q[2] = {s[P2[j][0]], s[P2[j][1]]};
+                if (simplex_owner(c, q, 2) != k || edge_id(c, q[0], q[1]) >= 0) continue;
+                c->ea[ne] = q[0];
+                c->eb[ne] = q[1];
+                const int64_t o = c->el_off[q[0]] + c->el_n[q[0]]++;
+                c->el_b[o] = q[1];
+                c->el_id[o] = ne++;
+            }
+            for (int j = 0; j < 4; ++j) {
+                int32_t q[3] = {s[P3[j][0]], s[P3[j][1]], s[P3[j][2]]};
+                if (simplex_owner(c, q, 3) != k || face_id(c, q[0], q[1], q[2]) >= 0) continue;
+                c->fa[nf] = q[0];
+                c->fb[nf] = q[1];
+                c->fc[nf] = q[2];
+                const int64_t o = c->fl_off[q[0]] + c->fl_n[q[0]]++;
+                c->fl_b[o] = q[1];
+                c->fl_c[o] = q[2];
+                c->fl_id[o] = nf++;
+            }
+        }
+        if (c->mutation == 10) relist_sorted(c, c->ie[k], ne, c->if_[k], nf);
+    }
+    c->ie[ncl] = ne;
+    c->if_[ncl] = nf;
+    c->ne = ne;
+    c->nf = nf;
+    free(star);
+    c->enumerated = 1;
+    return ORC_OK;
+}
+
+int64_t oracle_num_edges(const oracle_ctx *c) { return c->enumerated ? c->ne : -1; }
+int64_t oracle_num_faces(const oracle_ctx *c) { return c->enumerated ? c->nf : -1; }
+
+/* copy E (2 per edge), F (3 per triangle) and the interval arrays out */
+void oracle_simplices(const oracle_ctx *c, int32_t *e, int64_t *ie, int32_t *f, int64_t *if_) {
+    for (int64_t i = 0; i < c->ne; ++i) { e[2 * i] = c->ea[i]; e[2 * i + 1] = c->eb[i]; }
+    for (int64_t i = 0; i < c->nf; ++i) { f[3 * i] = c->fa[i]; f[3 * i + 1] = c->fb[i]; f[3 * i + 2] = c->fc[i]; }
+    memcpy(ie, c->ie, sizeof(int64_t) * (size_t)(c->ncl + 1));
+    memcpy(if_, c->if_, sizeof(int64_t) * (size_t)(c->ncl + 1));
+}
+
+/* number of elements common to two ascending lists, written to out */
+static int64_t intersect2(const int32_t *a, int64_t na, const int32_t *b, int64_t nb, int32_t *out) {
+    int64_t i = 0, j = 0, w = 0;
+    while (i < na && j < nb) {
+        if (a[i] == b[j]) { out[w++] = a[i]; ++i; ++j; }
+        else if (a[i] < b[j]) ++i;
+        else ++j;
+    }
+    return w;
+}
+
+static int reserve(oracle_buf *b, int64_t rows, int64_t ent);
+static int64_t intersect3(const int32_t *a, int64_t na, const int32_t *b, int64_t nb,
+                          const int32_t *c3, int64_t nc, int32_t *out);
+
+/* VE / VF / EF / ET / FT block of cluster k into b (the context must be
+ * enumerated) */
+static int cobound_block(const oracle_ctx *c, oracle_buf *b, int32_t k, int32_t rel, int64_t *nrows,
+                         int64_t *nnz) {
+    if (!c->enumerated) return ORC_EINVAL;
+    int64_t n, cap = 0;
+    if (rel == REL_VE || rel == REL_VF) {
+        n = c->vrow_off[k + 1] - c->vrow_off[k];
+        for (int64_t r = 0; r < n; ++r) {
+            const int32_t v = c->vrows[c->vrow_off[k] + r];
+            cap += 3 * (c->vt_off[v + 1] - c->vt_off[v]);
+        }
+    } else {
+        const int64_t *iv = rel == REL_FT ? c->if_ : c->ie;
+        n = iv[k + 1] - iv[k];
+        for (int64_t r = 0; r < n; ++r) {
+            const int64_t id = iv[k] + r;
+            const int32_t a = rel == REL_FT ? c->fa[id] : c->ea[id];
+            const int64_t d = c->vt_off[a + 1] - c->vt_off[a];
+            cap += (rel == REL_EF ? 2 : 1) * d;
+        }
+    }
+    if (reserve(b, n, cap + 1)) return ORC_ENOMEM;
+    int64_t w = 0;
+    b->off[0] = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t s0 = w;
+        if (rel == REL_VE || rel == REL_VF) {
+            const int32_t v = c->vrows[c->vrow_off[k] + r];
+            b->rows[r] = v;
+            for (int64_t i = c->vt_off[v]; i < c->vt_off[v + 1]; ++i) {
+                const int32_t *q = c->tv + 4 * (int64_t)c->vt[i];
+                int32_t o[3];
+                int m = 0;
+                for (int j = 0; j < 4; ++j)
+                    if (q[j] != v) o[m++] = q[j];
+                if (rel == REL_VE) {
+                    for (int j = 0; j < 3; ++j)
+                        b->ent[w++] = (int32_t)edge_id(c, v < o[j] ? v : o[j], v < o[j] ? o[j] : v);
+                } else {
+                    const int nfc = c->mutation == 12 ? 2 : 3;
+                    for (int j = 0; j < nfc; ++j) {
+                        /* the triangle of v and the two other vertices but o[j] */
+                        int32_t f[3] = {v, o[(j + 1) % 3], o[(j + 2) % 3]};
+                        for (int x = 1; x < 3; ++x)
+                            for (int y = x; y > 0 && f[y - 1] > f[y]; --y) {
+                                int32_t z = f[y]; f[y] = f[y - 1]; f[y - 1] = z;
+                            }
+                        b->ent[w++] = (int32_t)face_id(c, f[0], f[1], f[2]);
+                    }
+                }
+            }
+        } else if (rel == REL_EF || rel == REL_ET) {
+            const int64_t id = c->ie[k] + r;
+            const int32_t a = c->ea[id], e2 = c->eb[id];
+            b->rows[r] = (int32_t)id;
+            const int32_t *la = c->vt + c->vt_off[a];
+            const int32_t *lb = c->vt + c->vt_off[e2];
+            const int64_t na = c->vt_off[a + 1] - c->vt_off[a], nb = c->vt_off[e2 + 1] - c->vt_off[e2];
+            int64_t got = c->mutation == 13 ? (memcpy(b->ent + w, la, sizeof(int32_t) * (size_t)na), na)
+                                             : intersect2(la, na, lb, nb, b->ent + w);
+            if (rel == REL_ET) {
+                w += got;
+            } else {
+                /* the two triangles of each such tetrahedron that contain the edge */
+                int32_t *tl = (int32_t *)malloc(sizeof(int32_t) * (size_t)(got + 1));
+                memcpy(tl, b->ent + w, sizeof(int32_t) * (size_t)got);
+                for (int64_t i = 0; i < got; ++i) {
+                    const int32_t *q = c->tv + 4 * (int64_t)tl[i];
+                    for (int j = 0; j < 4; ++j) {
+                        if (q[j] == a || q[j] == e2) continue;
+                        int32_t f[3] = {a, e2, q[j]};
+                        for (int x = 1; x < 3; ++x)
+                            for (int y = x; y > 0 && f[y - 1] > f[y]; --y) {
+                                int32_t z = f[y]; f[y] = f[y - 1]; f[y - 1] = z;
+                            }
+                        b->ent[w++] = (int32_t)face_id(c, f[0], f[1], f[2]);
+                    }
+                }
+                free(tl);
+            }
+        } else {
+            const int64_t id = c->if_[k] + r;
+            const int32_t a = c->fa[id], b2 = c->fb[id], c3 = c->fc[id];
+            b->rows[r] = (int32_t)id;
+            w += intersect3(c->vt + c->vt_off[a], c->vt_off[a + 1] - c->vt_off[a], c->vt + c->vt_off[b2],
+                            c->vt_off[b2 + 1] - c->vt_off[b2], c->vt + c->vt_off[c3],
+                            c->vt_off[c3 + 1] - c->vt_off[c3], b->ent + w);
+        }
+        w = s0 + sort_unique(b->ent + s0, w - s0);
+        b->off[r + 1] = (int32_t)w;
+    }
+    *nrows = n;
+    *nnz = w;
+    b->nrows = n;
+    b->nnz = w;
+    return ORC_OK;
+}
+
 static int reserve(oracle_buf *b, int64_t rows, int64_t ent) {
     if (rows + 1 > b->cap_rows) {
         free(b->rows); free(b->off);
@@ -244,6 +561,8 @@ static int64_t intersect3(const int32_t *a, int64_t na, const int32_t *b, int64_
  * status; *nrows / *nnz receive the sizes.  Reads the context only. */
 int oracle_block_into(const oracle_ctx *c, oracle_buf *b, int32_t k, int32_t rel, int64_t *nrows, int64_t *nnz) {
     if (k < 0 || k >= c->ncl) return ORC_EINVAL;
+    if (rel == REL_VE || rel == REL_VF || rel == REL_EF || rel == REL_ET || rel == REL_FT)
+        return cobound_block(c, b, k, rel, nrows, nnz);
     if (rel != REL_VT && rel != REL_VV && rel != REL_TT) return ORC_EINVAL;
     if ((c->mutation == 3) != (c->owner_mut == 3)) return ORC_EINVAL;  /* owner table of another mutation */
     if (rel == REL_VT || rel == REL_VV) {
