@@ -243,6 +243,37 @@ gale_status gale_submit(gale_ctx *ctx, const int32_t *cluster_ids, int32_t n, ui
 gale_status gale_build(gale_ctx *ctx, const int32_t *cluster_ids, int32_t n, uint32_t rel_mask,
                        int32_t form, uint64_t *ticket_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): gale_build's
+ * BATCHED build of rel_mask for the n distinct clusters cluster_ids[0..n),
+ * into the caller's device buffer dev_out (out_words int32 words, 256-byte
+ * aligned), allocating no device memory.  Every other device buffer of the
+ * build (work list and queue words, block headers, the global path's
+ * workspace) lives in a static array of GALE_STATIC_SCRATCH_BYTES per GPU,
+ * set up by gale_create; a request that needs more (about 64 bytes per
+ * cluster plus one workspace slice of its largest global-path cluster) is
+ * EINVAL.  Calls on one GPU share that array: the library runs them one at a
+ * time in a process, and it keeps the last call's contents.
+ *   block_words (host, n + 1 int64, caller memory) receives the word offset
+ *   of cluster_ids[i]'s block in dev_out and, at [n], the words needed; it is
+ *   filled before anything is built.  With dev_out NULL or out_words below
+ *   block_words[n] the call returns ENOMEM and builds nothing (a size query).
+ * A block is laid out as an 8-word header {status, nV, nT, nnzVT, nnzVV,
+ * nnzTT, cap_vv, cap_tt}, then, each starting on a 32-word boundary, for the
+ * relations in rel_mask: VT|VV row ids [nV]; VT offsets [nV + 1] and entries
+ * [nnzVT]; TT row ids [nT], offsets [nT + 1] and entries [cap_tt]; VV offsets
+ * [nV + 1] and entries [cap_vv]; the contents equal gale_build's blocks.
+ * The build runs on the context stream and the call returns when it is done
+ * (synchronous).  When a block exceeds its capacity bound (non-manifold
+ * faces), the call returns ENOMEM with block_words holding the layout with
+ * that block's exact size, which the context remembers: call again with a
+ * buffer that large.  DIRECT mode.  Errors: EINVAL (as gale_build, a repeated
+ * cluster id, NULL block_words, scratch too small), ENOMEM (as above),
+ * ESTATE (no mesh, SERVE mode), EDEVICE. */
+#define GALE_STATIC_SCRATCH_BYTES (64ll << 20)
+gale_status gale_build_static(gale_ctx *ctx, const int32_t *cluster_ids, int32_t n, uint32_t rel_mask,
+                              int32_t *dev_out, int64_t out_words, int64_t *block_words);
+
 /* Choose how batched work runs by measurement: the analogue of the paper's
  * study of threads per segment, threads per block and blocks per request
  * (Appendix A; the kernel's block and thread parameters, Section 4.5).

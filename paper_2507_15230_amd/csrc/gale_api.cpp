@@ -946,6 +946,9 @@ gale_status gale_create(const gale_config *cfg_in, gale_ctx **out) {
     if (cfg.device < 0 || cfg.device >= ndev) return fail(GALE_EINVAL, "device ordinal out of range");
     e = hipSetDevice(cfg.device);
     if (e != hipSuccess) return fail(GALE_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    // the static scratch of gale_build_static: its address on this device, once
+    gale_status ss = static_scratch_setup(cfg.device);
+    if (ss) return ss;
     auto *ctx = new gale_ctx();
     ctx->cfg = cfg;
     if (cfg.tune_table_path) ctx->tune_path = cfg.tune_table_path;

@@ -239,6 +239,11 @@ struct gale_ctx {
     bool tune_applied = false;
     uint64_t n_timed = 0;     // timed persistent launches (under direct_mu)
     double kernel_ms = 0.0;   // their total duration
+    // gale_build_static: host staging of the work list and headers (reused),
+    // and exact (VV, TT) sizes of clusters whose blocks exceeded a bound
+    std::vector<char> static_host;
+    std::vector<int32_t> static_hdr;
+    std::unordered_map<int32_t, std::pair<int32_t, int32_t>> static_caps;
     gale::Serve serve;
 };
 
@@ -270,6 +275,11 @@ gale_status upload_and_launch(gale_ctx *ctx, int form, const std::vector<WorkIte
                               Buf *&dev_items, Buf *&dev_hdr, Buf *&host_items, Buf *&ws, hipStream_t st,
                               const hipEvent_t *kev = nullptr, bool *kev_recorded = nullptr);
 gale_status check_request(const gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t mask);
+
+// gale_build_static's device scratch: bytes per GPU, and the once-per-device
+// lookup of its address (gale_create, with the device current)
+constexpr int64_t kStaticScratchBytes = 64ll << 20;
+gale_status static_scratch_setup(int device);
 
 gale_status serve_start(gale_ctx *ctx);
 void serve_stop(gale_ctx *ctx);

@@ -123,6 +123,8 @@ def load_library(path: str = LIB_PATH):
         "gale_load": ([vp, C.c_int32, C.c_int64, i32p, i32p, C.c_int32], C.c_int32),
         "gale_submit": ([vp, i32p, C.c_int32, C.c_uint32, u64p], C.c_int32),
         "gale_build": ([vp, i32p, C.c_int32, C.c_uint32, C.c_int32, u64p], C.c_int32),
+        "gale_build_static": ([vp, i32p, C.c_int32, C.c_uint32, vp, C.c_int64, C.POINTER(C.c_int64)],
+                              C.c_int32),
         "gale_poll": ([vp, C.c_uint64, C.c_int64], C.c_int32),
         "gale_block": ([vp, C.c_uint64, C.c_int32, C.c_uint32, C.POINTER(GaleCsr)], C.c_int32),
         "gale_block_device": ([vp, C.c_uint64, C.c_int32, C.c_uint32, C.POINTER(GaleCsr)], C.c_int32),
@@ -240,6 +242,20 @@ class Context:
         f = {"plain": FORM_PLAIN, "batched": FORM_BATCHED}[form]
         _check(self._lib.gale_build(self._h, p, int(a.shape[0]), int(mask), f, C.byref(tk)), "gale_build")
         return tk.value
+
+    def build_static(self, ids, mask: int, dev_out: int, out_words: int):
+        """gale_build_static: build into the device buffer at address dev_out
+        (out_words int32 words) with no device allocation; returns (status,
+        block_words) where block_words[i] is the word offset of ids[i]'s block
+        and block_words[-1] the words needed (status ENOMEM: buffer too small,
+        nothing built)."""
+        a, p = _i32(np.atleast_1d(ids))
+        bw = np.zeros(a.shape[0] + 1, np.int64)
+        st = self._lib.gale_build_static(self._h, p, int(a.shape[0]), int(mask), dev_out or None, int(out_words),
+                                         bw.ctypes.data_as(C.POINTER(C.c_int64)))
+        if st not in (OK, ENOMEM):
+            _check(st, "gale_build_static")
+        return st, bw
 
     def poll(self, ticket: int, timeout_ns: int = -1) -> bool:
         st = self._lib.gale_poll(self._h, C.c_uint64(ticket), int(timeout_ns))
