@@ -198,6 +198,35 @@ def serving_leg(mesh, budget: int, consumers: int, ncur: int, front_end: str = "
     return out
 
 
+def simplices_leg(mesh, steps: int = 5) -> dict:
+    """The edge and triangle relations (VE, VF, EF, ET, FT) of every cluster
+    of `mesh`, built in the batched form into device memory: the lists' load
+    time (enumeration on the host and upload) and relation entries per second
+    over `steps` builds after one warm-up build."""
+    from paper_2507_15230_amd import gale
+    ctx = gale.Context(device=0, mode="direct", form="batched", simplex_lists=True)
+    ctx.load(mesh.tets, mesh.cluster, mesh.nclusters)
+    load_s = ctx.stats()["load_seconds"]
+    e, _, f, _ = ctx.simplices()
+    ids = np.arange(mesh.nclusters, dtype=np.int32)
+    t = ctx.build(ids, gale.REL_EXT)
+    ctx.poll(t)
+    ctx.release(t)
+    e0 = ctx.stats()["entries_built"]
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t = ctx.build(ids, gale.REL_EXT)
+        ctx.poll(t)
+        ctx.release(t)
+    dt = (time.perf_counter() - t0) / steps
+    ent = (ctx.stats()["entries_built"] - e0) // steps
+    ctx.close()
+    return {"relations": "VE+VF+EF+ET+FT", "edges": int(e.shape[0]), "triangles": int(f.shape[0]),
+            "load_seconds_with_lists": load_s, "entries_per_build": int(ent), "ms_per_build": dt * 1000.0,
+            "entries_per_s": ent / dt,
+            "note": "one gale_build per step (host staging and the header read-back included), device-resident output"}
+
+
 def summarize_profile(out_md, title, cmd_kt, kt_dir, cmd_fetch=None, fetch_dir=None, cmd_write=None,
                       write_dir=None, kernel_ms=None):
     """Turn rocprofv3 CSV output into a committed text summary: per-kernel
@@ -279,6 +308,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-simplices", action="store_true",
+                    help="skip the VE/VF/EF/ET/FT leg (on the 128^3 lattice, or the workload mesh for configs 1-2)")
     ap.add_argument("--tune-table", default=TUNE_TABLE, help="tune table read at load and written by autotune")
     ap.add_argument("--retune", action="store_true", help="run the autotuner even if the table has an entry")
     ap.add_argument("--consumers", type=int, default=40)
@@ -431,6 +462,14 @@ def main():
                 serving["runs"].append(serving_leg(mesh, b, args.consumers, ncur, fe, plain=(bi == 0 and fi == 0),
                                                    prefetch=args.prefetch))
 
+    simp = None
+    if not args.no_simplices:
+        log("edge / triangle relations")
+        smesh = mesh if args.config <= 2 else meshgen.config(2)
+        simp = simplices_leg(smesh)
+        simp["workload"] = WORKLOADS[args.config if args.config <= 2 else 2].split(";")[0]
+        del smesh
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -474,6 +513,7 @@ def main():
         "cpu_baseline": cpu,
         "plain": plain,
         "serving": serving,
+        "simplices": simp,
     }
     print(json.dumps(out), flush=True)
 

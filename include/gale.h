@@ -53,6 +53,26 @@ typedef int32_t gale_status;
 #define GALE_REL_VV 2u
 #define GALE_REL_TT 4u
 #define GALE_REL_ALL 7u
+/* The further coboundary relations (Section 2.2, Table 1), DIRECT mode, with
+ * gale_config.simplex_lists set:
+ *   VE  rows = the cluster's vertices; entries = ids of the edges containing
+ *       the vertex.
+ *   VF  rows = the cluster's vertices; entries = ids of the triangles
+ *       containing it.
+ *   EF  rows = the edges internal to the cluster (the smallest cluster among
+ *       an edge's vertices owns it, as for tetrahedra), listed by their ids;
+ *       entries = ids of the triangles containing the edge.
+ *   ET  rows as EF; entries = the tetrahedra containing the edge.
+ *   FT  rows = the triangles internal to the cluster; entries = the
+ *       tetrahedra containing the triangle.
+ * Edge and triangle ids are positions in the lists E and F of
+ * gale_get_simplices; entries ascending without repeats, as for VT/VV/TT. */
+#define GALE_REL_VE  8u
+#define GALE_REL_VF 16u
+#define GALE_REL_EF 32u
+#define GALE_REL_ET 64u
+#define GALE_REL_FT 128u
+#define GALE_REL_EXT 248u
 
 /* How gale_submit / gale_build execute a request. */
 #define GALE_FORM_PLAIN   0  /* one kernel launch per (cluster, relation) */
@@ -80,7 +100,9 @@ typedef struct {
                                      quarter (several workgroups per CU); each cluster takes the smallest shape its
                                      working set fits.  0 = the 1024-thread shape only.  Bit 3 (all forms): the
                                      global-memory path keeps every working array in global memory instead of
-                                     placing its most used ones in LDS when they fit (used by tests). */
+                                     placing its most used ones in LDS when they fit (used by tests).  Bit 4
+                                     (all forms): every cluster takes the global path, with that placement
+                                     when it fits (used by tests). */
     void    *hip_stream;          /* borrowed hipStream_t for DIRECT mode work, or NULL for a library-owned stream.
                                      Must outlive the context. */
     double   global_cu_share;     /* DIRECT mode, BATCHED form: share of the CUs (0 < s <= 1) the global-path
@@ -105,6 +127,10 @@ typedef struct {
     int32_t  front_end;           /* SERVE: GALE_FRONT_SINGLE (one queue, one service thread, a request's relations
                                      built by one kernel) or GALE_FRONT_PER_RELATION (one queue and one leader
                                      thread per relation, each building only its relation, Section 4.5) */
+    int32_t  simplex_lists;       /* nonzero: gale_load also enumerates the edge and triangle lists E, F and
+                                     their interval arrays (Section 4.3: built only when an algorithm needs edge
+                                     or triangle relations), which the VE, VF, EF, ET and FT relations and
+                                     gale_get_simplices need */
 } gale_config;
 
 #define GALE_FRONT_SINGLE       0
@@ -267,7 +293,7 @@ gale_status gale_build(gale_ctx *ctx, const int32_t *cluster_ids, int32_t n, uin
  * (synchronous).  When a block exceeds its capacity bound (non-manifold
  * faces), the call returns ENOMEM with block_words holding the layout with
  * that block's exact size, which the context remembers: call again with a
- * buffer that large.  DIRECT mode.  Errors: EINVAL (as gale_build, a repeated
+ * buffer that large.  DIRECT mode, VT|VV|TT.  Errors: EINVAL (as gale_build, a repeated
  * cluster id, NULL block_words, scratch too small), ENOMEM (as above),
  * ESTATE (no mesh, SERVE mode), EDEVICE. */
 #define GALE_STATIC_SCRATCH_BYTES (64ll << 20)
@@ -360,6 +386,27 @@ void *gale_stream(gale_ctx *ctx);
  * *out is caller memory.  Errors: EINVAL (NULL, cluster out of range),
  * ESTATE (no mesh loaded).  Thread-safe. */
 gale_status gale_get_cluster_info(gale_ctx *ctx, int32_t cluster, gale_cluster_info *out);
+
+/* The edge and triangle lists of the loaded mesh (gale_config.simplex_lists),
+ * as the initialization step enumerates them (Section 4.3): edge i is
+ * (e[2i], e[2i+1]) and triangle i is (f[3i], f[3i+1], f[3i+2]), each with
+ * ascending original vertex ids; the edges internal to cluster k are ids
+ * ie[k] .. ie[k+1]-1 and its triangles if_[k] .. if_[k+1]-1 (the interval
+ * arrays I_E, I_F).  Numbering: for each cluster in turn, its tetrahedra
+ * (those with a vertex in it) in ascending id, each tetrahedron's vertex
+ * pairs (triples) in lexicographic order of its ascending vertices; an edge
+ * (triangle) internal to the cluster takes the next id when first met.  This
+ * is the reading of Section 4.3 under which the example of Section 4.4 holds
+ * (I_E = 0, 9, 12; f5 = v0 v3 v4; FE(f5) = e2, e6, e9).  The pointers are
+ * library-owned host memory valid until gale_destroy.  Errors: EINVAL (NULL),
+ * ESTATE (no mesh, or loaded without simplex_lists). */
+typedef struct {
+    int64_t ne, nf;
+    int32_t ncl, pad;
+    const int32_t *e, *f;
+    const int64_t *ie, *if_;
+} gale_simplices;
+gale_status gale_get_simplices(gale_ctx *ctx, gale_simplices *out);
 
 /* Text of a status code (static storage). */
 const char *gale_strerror(gale_status s);

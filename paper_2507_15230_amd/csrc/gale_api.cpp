@@ -89,11 +89,16 @@ int64_t lay_out_items(const gale_ctx *ctx, std::vector<WorkItem> &items, int64_t
     for (size_t i = 0; i < items.size(); ++i) {
         WorkItem &it = items[i];
         const ClusterMeta &m = ctx->meta[it.cluster];
+        it.out_word = w;
+        it.hdr_index = (int32_t)i;
+        if (it.mask & kRelExt) {  // edge / triangle relations: their own block
+            it.cap_vv = it.cap_tt = 0;
+            w += ext_layout(it.mask, m, ctx->sx.ext[it.cluster]).total;
+            continue;
+        }
         if (it.cap_vv < 0) it.cap_vv = (it.mask & kRelVV) ? m.cap_vv : 0;
         if (it.cap_tt < 0) it.cap_tt = (it.mask & kRelTT) ? default_cap_tt(m) : 0;
         const BlockLayout lay = block_layout(it.mask, m.nV, m.nT, m.nnzVT, it.cap_vv, it.cap_tt);
-        it.out_word = w;
-        it.hdr_index = (int32_t)i;
         w += lay.total;
     }
     return w - out_base_word;
@@ -142,6 +147,7 @@ void setup_global(gale_ctx *ctx, int bt) {
 // The workgroup shape of an item: the smallest (last) launch class whose LDS
 // plan fits, or -1 for the global-workspace path.
 int item_class(const gale_ctx *ctx, const WorkItem &it) {
+    if (ctx->cfg.launch_classes & 16) return -1;  // every cluster on the global path (tests)
     for (int c = (int)ctx->classes.size() - 1; c >= 0; --c) {
         const gale_ctx::LaunchClass &lc = ctx->classes[c];
         if (lds_plan(ctx->meta[it.cluster], it.mask, lc.budget, lc.bt).ok) return c;
@@ -172,6 +178,11 @@ KArgs base_args(const gale_ctx *ctx) {
     a.s.tid = ctx->d_tid;
     a.s.lverts = ctx->d_lverts;
     a.s.meta = ctx->d_meta;
+    a.x.ext = ctx->d_ext;
+    a.x.eoff = ctx->d_eoff;
+    a.x.eidx = ctx->d_eidx;
+    a.x.foff = ctx->d_foff;
+    a.x.fidx = ctx->d_fidx;
     a.lds_budget = (int32_t)ctx->lds_budget;
     return a;
 }
@@ -339,8 +350,12 @@ gale_status stage_items(gale_ctx *ctx, int form, const std::vector<WorkItem> &it
         if (hyb_plan(ctx->meta[order[i].cluster], order[i].mask, ctx->glob_lds, ctx->glob_bt).ok)
             ctx->n_hybrid_blocks++;
     const int slots = form == GALE_FORM_PLAIN ? 1 : std::min<int>(std::max(n_glob, 1), glob_grid);
+    // headers are written at each item's hdr_index, which may range over a
+    // batch's edge / triangle items too
+    size_t nh = (size_t)n;
+    for (const WorkItem &it : items) nh = std::max(nh, (size_t)it.hdr_index + 1);
     dev_items = ctx->dev_pool.acquire((size_t)n * sizeof(WorkItem) + 64, &e);
-    dev_hdr = ctx->dev_pool.acquire((size_t)n * 32 + 64, &e);
+    if (!dev_hdr) dev_hdr = ctx->dev_pool.acquire(nh * 32 + 64, &e);
     host_items = ctx->pin_pool.acquire((size_t)n * sizeof(WorkItem) + 64, &e);
     if (!dev_items || !dev_hdr || !host_items) return fail(GALE_ENOMEM, "batch buffers");
     if (n_glob > 0) {
@@ -371,6 +386,48 @@ gale_status upload_and_launch(gale_ctx *ctx, int form, const std::vector<WorkIte
                         kev, kev_recorded);
 }
 
+// Edge / triangle relation items (laid out, hdr_index set): their work list
+// with one queue word per launch copied to the device, a workspace slice per
+// workgroup, then one persistent launch over all of them (BATCHED) or one
+// launch per item (PLAIN), after whatever st already holds.
+gale_status launch_ext_items(gale_ctx *ctx, Batch &b, int form, const std::vector<WorkItem> &items, hipStream_t st) {
+    hipError_t e = hipSuccess;
+    const int n = (int)items.size();
+    if (n == 0) return GALE_OK;
+    const int nq = form == GALE_FORM_PLAIN ? n : 1;
+    const size_t qbytes = ((size_t)nq * 4 + 63) / 64 * 64;
+    int64_t wsb = 256;
+    for (const WorkItem &it : items)
+        wsb = std::max<int64_t>(wsb, ext_workspace_bytes(ctx->meta[it.cluster], ctx->sx.ext[it.cluster], it.mask));
+    int occ = 4;
+    const int grid = form == GALE_FORM_PLAIN ? 1 : std::max(1, std::min(n, ctx->num_cus * occ));
+    b.ext_items = ctx->dev_pool.acquire(qbytes + (size_t)n * sizeof(WorkItem), &e);
+    b.ext_host = ctx->pin_pool.acquire(qbytes + (size_t)n * sizeof(WorkItem), &e);
+    b.ext_ws = ctx->dev_pool.acquire((size_t)wsb * grid, &e);
+    if (!b.ext_items || !b.ext_host || !b.ext_ws) return fail(GALE_ENOMEM, "edge / triangle work buffers");
+    char *hi = (char *)b.ext_host->ptr;
+    std::memset(hi, 0, qbytes);
+    std::memcpy(hi + qbytes, items.data(), (size_t)n * sizeof(WorkItem));
+    e = hipMemcpyAsync(b.ext_items->ptr, hi, qbytes + (size_t)n * sizeof(WorkItem), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return fail(GALE_EDEVICE, std::string("work list copy: ") + hipGetErrorString(e));
+    KArgs a = base_args(ctx);
+    a.out = (int32_t *)b.out->ptr;
+    a.hdr = (int32_t *)b.dev_hdr->ptr;
+    a.ws = (char *)b.ext_ws->ptr;
+    a.ws_stride = wsb;
+    const WorkItem *di = (const WorkItem *)((char *)b.ext_items->ptr + qbytes);
+    int32_t *dq = (int32_t *)b.ext_items->ptr;
+    for (int l = 0; l < nq && e == hipSuccess; ++l) {
+        a.items = di + (form == GALE_FORM_PLAIN ? l : 0);
+        a.nitems = form == GALE_FORM_PLAIN ? 1 : n;
+        a.queue = dq + l;
+        e = launch_ext(a, grid, st);
+        ctx->n_launches++;
+    }
+    if (e != hipSuccess) return fail(GALE_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return GALE_OK;
+}
+
 // Lay out the batch's items in a fresh output buffer and launch them.
 gale_status run_items(gale_ctx *ctx, Batch &b, int form, hipStream_t st) {
     hipError_t e;
@@ -381,8 +438,18 @@ gale_status run_items(gale_ctx *ctx, Batch &b, int form, hipStream_t st) {
     b.host_hdr = ctx->pin_pool.acquire((size_t)n * 32 + 64, &e);
     if (!b.host_hdr) return fail(GALE_ENOMEM, "batch buffers");
     if (n == 0) return GALE_OK;
-    return upload_and_launch(ctx, form, b.items, (int32_t *)b.out->ptr, b.dev_items, b.dev_hdr, b.host_items, b.ws,
-                             st, b.kev[0] ? b.kev : nullptr, &b.kev_recorded);
+    std::vector<WorkItem> base, ext;
+    for (const WorkItem &it : b.items) ((it.mask & kRelExt) ? ext : base).push_back(it);
+    if (!ext.empty()) {
+        b.dev_hdr = ctx->dev_pool.acquire((size_t)n * 32 + 64, &e);
+        if (!b.dev_hdr) return fail(GALE_ENOMEM, "batch buffers");
+    }
+    gale_status s = GALE_OK;
+    if (!base.empty())
+        s = upload_and_launch(ctx, form, base, (int32_t *)b.out->ptr, b.dev_items, b.dev_hdr, b.host_items, b.ws, st,
+                              b.kev[0] ? b.kev : nullptr, &b.kev_recorded);
+    if (!s) s = launch_ext_items(ctx, b, form, ext, st);
+    return s;
 }
 
 void release_batch(gale_ctx *ctx, Batch &b) {
@@ -390,6 +457,10 @@ void release_batch(gale_ctx *ctx, Batch &b) {
         b.out = b.dev_items = b.dev_hdr = b.ws = b.host_items = b.host_hdr = b.host_out = nullptr;
         return;
     }
+    ctx->dev_pool.release(b.ext_items);
+    ctx->dev_pool.release(b.ext_ws);
+    ctx->pin_pool.release(b.ext_host);
+    b.ext_items = b.ext_ws = b.ext_host = nullptr;
     ctx->dev_pool.release(b.out);
     ctx->dev_pool.release(b.dev_items);
     ctx->dev_pool.release(b.dev_hdr);
@@ -398,6 +469,24 @@ void release_batch(gale_ctx *ctx, Batch &b) {
     ctx->pin_pool.release(b.host_hdr);
     ctx->pin_pool.release(b.host_out);
     b.out = b.dev_items = b.dev_hdr = b.ws = b.host_items = b.host_hdr = b.host_out = nullptr;
+}
+
+// relation entries of a finalized batch's blocks (from their headers)
+uint64_t batch_entries(const Batch &b) {
+    uint64_t ent = 0;
+    for (size_t i = 0; i < b.items.size(); ++i) {
+        const int32_t *h = &b.hdr[i * 8];
+        const uint32_t mk = b.items[i].mask;
+        if (mk & kRelExt) {
+            for (int r = 0; r < 5; ++r)
+                if (mk & (kRelVE << r)) ent += (uint64_t)h[1 + r];
+            continue;
+        }
+        if (mk & kRelVT) ent += (uint64_t)h[3];
+        if (mk & kRelVV) ent += (uint64_t)h[4];
+        if (mk & kRelTT) ent += (uint64_t)h[5];
+    }
+    return ent;
 }
 
 // After the batch's kernels finished: read the headers, rebuild the blocks
@@ -451,14 +540,7 @@ gale_status finalize_batch(gale_ctx *ctx, Batch &b, hipStream_t st) {
         r.out = nullptr;
         release_batch(ctx, r);
     }
-    uint64_t ent = 0;
-    for (int i = 0; i < n; ++i) {
-        const int32_t *h = &b.hdr[(size_t)i * 8];
-        if (b.items[i].mask & kRelVT) ent += (uint64_t)h[3];
-        if (b.items[i].mask & kRelVV) ent += (uint64_t)h[4];
-        if (b.items[i].mask & kRelTT) ent += (uint64_t)h[5];
-    }
-    ctx->n_entries += ent;
+    ctx->n_entries += batch_entries(b);
     ctx->n_blocks += n;
     return GALE_OK;
 }
@@ -469,41 +551,36 @@ gale_status copy_batch_to_host(gale_ctx *ctx, Batch &b, hipStream_t st) {
     int64_t words = 0;
     const int n = (int)b.items.size();
     b.host_word.assign(n, 0);
-    for (int i = 0; i < n; ++i) {
-        const ClusterMeta &m = ctx->meta[b.items[i].cluster];
+    // exact used size: VV is last, so its tail beyond the real count is
+    // skipped; an edge / triangle block is copied whole
+    auto used_words = [&](int i) -> int64_t {
+        const WorkItem &it = b.items[i];
+        const ClusterMeta &m = ctx->meta[it.cluster];
+        if (it.mask & kRelExt) return ext_layout(it.mask, m, ctx->sx.ext[it.cluster]).total;
         const int32_t *h = &b.hdr[(size_t)i * 8];
-        // exact used size: VV is last, so its tail beyond the real count is skipped
-        const int32_t used_vv = (b.items[i].mask & kRelVV) ? h[4] : 0;
-        const BlockLayout lay = block_layout(b.items[i].mask, m.nV, m.nT, m.nnzVT, used_vv, b.items[i].cap_tt);
+        const int32_t used_vv = (it.mask & kRelVV) ? h[4] : 0;
+        return block_layout(it.mask, m.nV, m.nT, m.nnzVT, used_vv, it.cap_tt).total;
+    };
+    for (int i = 0; i < n; ++i) {
         b.host_word[i] = words;
-        words += lay.total;
+        words += used_words(i);
     }
     hipError_t e;
     b.host_out = ctx->pin_pool.acquire((size_t)words * 4 + 256, &e);
     if (!b.host_out) return fail(GALE_ENOMEM, "pinned host buffer");
     uint64_t bytes = 0;
     for (int i = 0; i < n; ++i) {
-        const ClusterMeta &m = ctx->meta[b.items[i].cluster];
-        const int32_t *h = &b.hdr[(size_t)i * 8];
-        const int32_t used_vv = (b.items[i].mask & kRelVV) ? h[4] : 0;
-        const BlockLayout lay = block_layout(b.items[i].mask, m.nV, m.nT, m.nnzVT, used_vv, b.items[i].cap_tt);
+        const int64_t wds = used_words(i);
         const int32_t *src = (const int32_t *)b.loc[i].buf->ptr + b.loc[i].word;
         int32_t *dst = (int32_t *)b.host_out->ptr + b.host_word[i];
-        e = hipMemcpyAsync(dst, src, (size_t)lay.total * 4, hipMemcpyDeviceToHost, st);
+        e = hipMemcpyAsync(dst, src, (size_t)wds * 4, hipMemcpyDeviceToHost, st);
         if (e != hipSuccess) return fail(GALE_EDEVICE, std::string("block copy: ") + hipGetErrorString(e));
-        bytes += (uint64_t)lay.total * 4;
+        bytes += (uint64_t)wds * 4;
     }
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(GALE_EDEVICE, std::string("block copy: ") + hipGetErrorString(e));
     ctx->n_bytes_d2h += bytes;
-    uint64_t ent = 0;
-    for (int i = 0; i < n; ++i) {
-        const int32_t *h = &b.hdr[(size_t)i * 8];
-        if (b.items[i].mask & kRelVT) ent += (uint64_t)h[3];
-        if (b.items[i].mask & kRelVV) ent += (uint64_t)h[4];
-        if (b.items[i].mask & kRelTT) ent += (uint64_t)h[5];
-    }
-    ctx->n_delivered += ent;
+    ctx->n_delivered += batch_entries(b);
     b.host_ready = true;
     return GALE_OK;
 }
@@ -513,6 +590,23 @@ gale_status block_view(const gale_ctx *ctx, const Batch &b, int i, uint32_t rel,
     const WorkItem &it = b.items[i];
     const ClusterMeta &m = ctx->meta[it.cluster];
     const int32_t *h = &b.hdr[(size_t)i * 8];
+    if (it.mask & kRelExt) {
+        if (host && !b.host_ready) return fail(GALE_ESTATE, "ticket has no host copy (made with gale_build)");
+        const ExtLayout lay = ext_layout(it.mask, m, ctx->sx.ext[it.cluster]);
+        const int32_t *base = host ? (const int32_t *)b.host_out->ptr + b.host_word[i]
+                                   : (const int32_t *)b.loc[i].buf->ptr + b.loc[i].word;
+        int r = 0;
+        while (r < 5 && rel != (kRelVE << r)) ++r;
+        out->cluster = it.cluster;
+        out->rel = rel;
+        out->pad = 0;
+        out->nrows = lay.nrows[r];
+        out->nnz = h[1 + r];
+        out->row_ids = base + lay.rows[r];
+        out->offsets = base + lay.off[r];
+        out->entries = base + lay.ent[r];
+        return GALE_OK;
+    }
     const int32_t *base;
     BlockLayout lay;
     if (host) {
@@ -555,7 +649,12 @@ gale_status block_view(const gale_ctx *ctx, const Batch &b, int i, uint32_t rel,
 gale_status check_request(const gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t mask) {
     if (!ctx->loaded) return fail(GALE_ESTATE, "no mesh loaded");
     if (n < 0 || (n > 0 && !ids)) return fail(GALE_EINVAL, "bad cluster id list");
-    if (mask == 0 || (mask & ~GALE_REL_ALL)) return fail(GALE_EINVAL, "relation mask must be a non-empty subset of VT|VV|TT");
+    if (mask == 0 || (mask & ~(GALE_REL_ALL | GALE_REL_EXT)))
+        return fail(GALE_EINVAL, "relation mask must be a non-empty subset of VT|VV|TT|VE|VF|EF|ET|FT");
+    if ((mask & GALE_REL_EXT) && !ctx->has_simplices)
+        return fail(GALE_ESTATE, "edge / triangle relations need gale_config.simplex_lists at load");
+    if ((mask & GALE_REL_EXT) && ctx->cfg.mode == GALE_MODE_SERVE)
+        return fail(GALE_EINVAL, "SERVE mode builds VT, VV and TT");
     for (int32_t i = 0; i < n; ++i)
         if (ids[i] < 0 || ids[i] >= ctx->ncl)
             return fail(GALE_EINVAL, "cluster id " + std::to_string(ids[i]) + " out of range");
@@ -579,7 +678,7 @@ std::vector<WorkItem> make_items(const gale_ctx *ctx, const int32_t *ids, int32_
     };
     if (form == GALE_FORM_PLAIN) {
         for (int32_t k : u)
-            for (uint32_t bit : {kRelVT, kRelVV, kRelTT})
+            for (uint32_t bit : {kRelVT, kRelVV, kRelTT, kRelVE, kRelVF, kRelEF, kRelET, kRelFT})
                 if (mask & bit) mk(k, bit);
     } else {
         std::stable_sort(u.begin(), u.end(), [&](int32_t x, int32_t y) {
@@ -587,7 +686,12 @@ std::vector<WorkItem> make_items(const gale_ctx *ctx, const int32_t *ids, int32_
             const int64_t cy = (int64_t)ctx->meta[y].ns + ctx->meta[y].nh;
             return cx > cy;
         });
-        for (int32_t k : u) mk(k, mask);
+        // VT / VV / TT in one item per cluster, the edge and triangle
+        // relations in another (a kernel of their own)
+        if (mask & kRelBase)
+            for (int32_t k : u) mk(k, mask & kRelBase);
+        if (mask & kRelExt)
+            for (int32_t k : u) mk(k, mask & kRelExt);
     }
     return items;
 }
@@ -747,6 +851,7 @@ bool write_tune_entry(const std::string &path, const TuneEntry &te) {
 gale_status graph_create(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t mask, uint64_t *out) {
     gale_status s = check_request(ctx, ids, n, mask);
     if (s) return s;
+    if (mask & kRelExt) return fail(GALE_EINVAL, "graphs capture VT, VV and TT requests");
     if (ctx->poisoned) return fail(GALE_EDEVICE, "context poisoned by an earlier device error");
     auto *g = new Prepared();
     g->batch.items = make_items(ctx, ids, n, mask, GALE_FORM_BATCHED);
@@ -1050,6 +1155,31 @@ gale_status gale_load(gale_ctx *ctx, int32_t nv, int64_t nt, const int32_t *tv, 
                     std::string("mesh upload: ") + hipGetErrorString(e));
     }
     ctx->mesh_bytes = hs.tets.size() + (hs.tid.size() + hs.lverts.size()) * 4 + hs.meta.size() * sizeof(ClusterMeta);
+    if (ctx->cfg.simplex_lists) {
+        // the edge and triangle lists (Section 4.3), their index by smallest
+        // vertex and the per-cluster ranges, on the GPU; E, F and the
+        // interval arrays stay on the host for gale_get_simplices
+        s = enumerate_simplices(hs, ctx->sx, err);
+        if (s) return fail(s, err);
+        HostSimplices &x = ctx->sx;
+        e = up((void **)&ctx->d_ext, x.ext.data(), x.ext.size() * sizeof(ExtMeta));
+        if (e == hipSuccess) e = up((void **)&ctx->d_eoff, x.eoff.data(), x.eoff.size() * 4);
+        if (e == hipSuccess) e = up((void **)&ctx->d_eidx, x.eidx.data(), x.eidx.size() * 4);
+        if (e == hipSuccess) e = up((void **)&ctx->d_foff, x.foff.data(), x.foff.size() * 4);
+        if (e == hipSuccess) e = up((void **)&ctx->d_fidx, x.fidx.data(), x.fidx.size() * 4);
+        if (e != hipSuccess) {
+            ctx->poisoned = true;
+            return fail(e == hipErrorOutOfMemory ? GALE_ENOMEM : GALE_EDEVICE,
+                        std::string("edge / triangle list upload: ") + hipGetErrorString(e));
+        }
+        ctx->mesh_bytes += (x.eoff.size() + x.eidx.size() + x.foff.size() + x.fidx.size()) * 4 +
+                           x.ext.size() * sizeof(ExtMeta);
+        std::vector<int32_t>().swap(x.eoff);
+        std::vector<int32_t>().swap(x.eidx);
+        std::vector<int32_t>().swap(x.foff);
+        std::vector<int32_t>().swap(x.fidx);
+        ctx->has_simplices = true;
+    }
     ctx->stream_tets = (int64_t)hs.tid.size();
     ctx->meta = std::move(hs.meta);
     ctx->nv = nv;
@@ -1116,7 +1246,8 @@ gale_status gale_poll(gale_ctx *ctx, uint64_t ticket, int64_t timeout_ns) {
 
 static gale_status view(gale_ctx *ctx, uint64_t ticket, int32_t cluster, uint32_t rel, bool host, gale_csr *out) {
     if (!ctx || !out) return fail(GALE_EINVAL, "NULL argument");
-    if (rel != GALE_REL_VT && rel != GALE_REL_VV && rel != GALE_REL_TT) return fail(GALE_EINVAL, "rel must be one bit");
+    if (rel == 0 || (rel & (rel - 1)) || (rel & ~(GALE_REL_ALL | GALE_REL_EXT)))
+        return fail(GALE_EINVAL, "rel must be one relation bit");
     if (ctx->cfg.mode == GALE_MODE_SERVE) {
         if (!host) return fail(GALE_ESTATE, "SERVE mode tickets have host views only");
         return serve_block(ctx, ticket, cluster, rel, out);
@@ -1176,6 +1307,7 @@ gale_status gale_autotune(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t
     if (reps < 1) return fail(GALE_EINVAL, "reps must be >= 1");
     gale_status st = check_request(ctx, ids, n, mask);
     if (st) return st;
+    if (mask & kRelExt) return fail(GALE_EINVAL, "autotune times VT, VV and TT requests");
     const int candidates[4] = {0, 2, 4, 6};
     double ms[4] = {0, 0, 0, 0};
     uint64_t saved_n;
@@ -1346,6 +1478,22 @@ gale_status gale_get_cluster_info(gale_ctx *ctx, int32_t cluster, gale_cluster_i
     return GALE_OK;
 }
 
+gale_status gale_get_simplices(gale_ctx *ctx, gale_simplices *out) {
+    if (!ctx || !out) return fail(GALE_EINVAL, "NULL argument");
+    if (!ctx->loaded || !ctx->has_simplices)
+        return fail(GALE_ESTATE, "no mesh loaded with gale_config.simplex_lists");
+    const HostSimplices &x = ctx->sx;
+    out->ne = (int64_t)x.e.size() / 2;
+    out->nf = (int64_t)x.f.size() / 3;
+    out->ncl = ctx->ncl;
+    out->pad = 0;
+    out->e = x.e.data();
+    out->f = x.f.data();
+    out->ie = x.ie.data();
+    out->if_ = x.if_.data();
+    return GALE_OK;
+}
+
 gale_status gale_reset_stats(gale_ctx *ctx) {
     if (!ctx) return fail(GALE_EINVAL, "ctx is NULL");
     {
@@ -1384,6 +1532,9 @@ void gale_destroy(gale_ctx *ctx) {
     if (ctx->d_tid) (void)hipFree(ctx->d_tid);
     if (ctx->d_lverts) (void)hipFree(ctx->d_lverts);
     if (ctx->d_meta) (void)hipFree(ctx->d_meta);
+    for (void *p : {(void *)ctx->d_ext, (void *)ctx->d_eoff, (void *)ctx->d_eidx, (void *)ctx->d_foff,
+                    (void *)ctx->d_fidx})
+        if (p) (void)hipFree(p);
     for (hipStream_t s2 : ctx->aux) (void)hipStreamDestroy(s2);
     for (hipEvent_t ev : ctx->join_ev) (void)hipEventDestroy(ev);
     if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);

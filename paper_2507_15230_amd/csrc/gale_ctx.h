@@ -56,6 +56,8 @@ struct Batch {
     hipEvent_t kev[2] = {nullptr, nullptr};  // around the persistent launches (DIRECT, BATCHED)
     bool kev_recorded = false;
     bool borrowed = false;  // buffers owned by a prepared (graph) request, not by this batch
+    // edge / triangle relation items (their own work list and workspace)
+    Buf *ext_items = nullptr, *ext_host = nullptr, *ext_ws = nullptr;
 };
 
 struct Ticket {
@@ -225,6 +227,12 @@ struct gale_ctx {
     uint8_t *d_tets = nullptr;
     int32_t *d_tid = nullptr, *d_lverts = nullptr;
     gale::ClusterMeta *d_meta = nullptr;
+    // edge and triangle lists (gale_config.simplex_lists): host copies of E,
+    // F and the interval arrays, the per-cluster ranges, and the device index
+    bool has_simplices = false;
+    gale::HostSimplices sx;
+    gale::ExtMeta *d_ext = nullptr;
+    int32_t *d_eoff = nullptr, *d_eidx = nullptr, *d_foff = nullptr, *d_fidx = nullptr;
     // pools and tickets
     gale::Pool dev_pool, pin_pool;
     std::mutex direct_mu, tick_mu;

@@ -22,6 +22,19 @@ struct HostStreams {
     std::vector<int32_t> lverts;  // original id | row << 31
 };
 
+// Edge and triangle lists of the initialization step (enumerate_simplices):
+// e / f hold 2 / 3 original ids per edge / triangle by id; ie / if_ the
+// interval arrays; eoff, eidx, foff, fidx the index by smallest vertex (see
+// Simplices in gale_layout.h); ext the per-cluster ranges and counts.
+struct HostSimplices {
+    std::vector<int32_t> e, f;
+    std::vector<int64_t> ie, if_;
+    std::vector<int32_t> eoff, foff, eidx, fidx;
+    std::vector<ExtMeta> ext;
+};
+
+gale_status enumerate_simplices(const HostStreams &hs, HostSimplices &out, std::string &err);
+
 gale_status prepare_streams(int32_t nv, int64_t nt, const int32_t *tv, const int32_t *cl, int32_t ncl,
                             HostStreams &out, std::string &err);
 
@@ -33,5 +46,10 @@ hipError_t set_lds_limits(size_t lds);
 hipError_t launch_zero(int32_t *p, int n, hipStream_t st);  // n <= 64
 hipError_t static_lds_bytes(int64_t *bytes);  // largest static LDS of the LDS-path kernels
 hipError_t persistent_occupancy(int block_threads, bool lds_path, size_t lds, int *blocks_per_cu);
+// the edge / triangle relation kernel (persistent over a.items, workspace
+// slices of a.ws_stride bytes per workgroup)
+hipError_t launch_ext(const KArgs &a, int grid, hipStream_t st);
+int64_t ext_workspace_bytes(const ClusterMeta &m, const ExtMeta &x, uint32_t mask);
+constexpr int kExtThreads = 512;
 
 }  // namespace gale

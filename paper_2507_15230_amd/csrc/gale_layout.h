@@ -45,6 +45,9 @@ namespace gale {
 #define GALE_HD __host__ __device__ __forceinline__
 
 constexpr uint32_t kRelVT = 1u, kRelVV = 2u, kRelTT = 4u;
+// the further coboundary relations, built from the edge and triangle lists
+constexpr uint32_t kRelVE = 8u, kRelVF = 16u, kRelEF = 32u, kRelET = 64u, kRelFT = 128u;
+constexpr uint32_t kRelBase = 7u, kRelExt = 0xF8u;
 constexpr int kHeaderWords = 8;
 constexpr int kAlignWords = 32;
 
@@ -88,6 +91,41 @@ struct BlockLayout {
     int64_t total;  // words
 };
 
+// Per cluster, for the edge and triangle relations: the cluster's internal
+// edges are ids [e0, e0 + ne), its internal triangles [f0, f0 + nf) (the
+// interval arrays I_E, I_F of the initialization step); et_inst and ft_inst
+// count the (tetrahedron, internal edge) and (tetrahedron, internal triangle)
+// pairs of its star, i.e. the entries of its ET and FT blocks.
+struct ExtMeta {
+    int32_t e0, ne, f0, nf;
+    int32_t et_inst, ft_inst;
+    int32_t pad[2];
+};
+static_assert(sizeof(ExtMeta) == 32, "ExtMeta layout");
+
+// Block of the edge and triangle relations (one cluster, the relations of a
+// mask within kRelExt): header[8] = {status, nnz VE, VF, EF, ET, FT, 0, 0},
+// then for each relation of the mask in the order VE, VF, EF, ET, FT, each
+// array on a 32-word boundary: row ids[nrows], offsets[nrows + 1],
+// entries[capacity].  Rows: VE, VF the cluster's vertices (original ids,
+// ascending); EF, ET its internal edges (edge ids e0 ..); FT its internal
+// triangles (triangle ids f0 ..).  Capacities (bounds the host and kernel
+// both derive): VE and VF 3 nnzVT (three per (tetrahedron, row vertex) pair),
+// EF 2 et_inst, ET et_inst, FT ft_inst (exact).
+struct ExtLayout {
+    int64_t rows[5], off[5], ent[5];
+    int32_t nrows[5], cap[5];
+    int64_t total;  // words
+};
+
+GALE_HD int32_t ext_nrows(int r, const ClusterMeta &m, const ExtMeta &x) {
+    return r <= 1 ? m.nV : (r <= 3 ? x.ne : x.nf);
+}
+
+GALE_HD int32_t ext_cap(int r, const ClusterMeta &m, const ExtMeta &x) {
+    return r <= 1 ? 3 * m.nnzVT : (r == 2 ? 2 * x.et_inst : (r == 3 ? x.et_inst : x.ft_inst));
+}
+
 struct Streams {
     const char *tets;        // stream tetrahedra (see ClusterMeta::tb_off, flags)
     const int32_t *tid;      // original tetrahedron id | internal << 31
@@ -95,9 +133,19 @@ struct Streams {
     const ClusterMeta *meta;
 };
 
+// Edge and triangle lists indexed by smallest vertex (original ids): edges
+// {a < b} of vertex a at eidx[2 eoff[a] .. 2 eoff[a+1]) as (b, id) sorted by
+// b; triangles {a < b < c} at fidx[4 foff[a] ..) as (b, c, id, 0) sorted by
+// (b, c).
+struct Simplices {
+    const ExtMeta *ext;
+    const int32_t *eoff, *eidx, *foff, *fidx;
+};
+
 // Kernel arguments (passed by value).
 struct KArgs {
     Streams s;
+    Simplices x;
     int32_t *out;            // output buffer (words)
     int32_t *hdr;            // compact header copies, 8 words per item (may be null)
     const WorkItem *items;
@@ -128,6 +176,25 @@ GALE_HD BlockLayout block_layout(uint32_t mask, int32_t nV, int32_t nT, int32_t 
     if (mask & kRelVV) {
         b.vv_off = w; w = align_words(w + nV + 1);
         b.vv_ent = w; w = align_words(w + cap_vv);
+    }
+    b.total = w;
+    return b;
+}
+
+GALE_HD ExtLayout ext_layout(uint32_t mask, const ClusterMeta &m, const ExtMeta &x) {
+    ExtLayout b;
+    int64_t w = align_words(kHeaderWords);
+    for (int r = 0; r < 5; ++r) {
+        b.nrows[r] = ext_nrows(r, m, x);
+        b.cap[r] = ext_cap(r, m, x);
+        b.rows[r] = b.off[r] = b.ent[r] = -1;
+        if (!(mask & (kRelVE << r))) continue;
+        b.rows[r] = w;
+        w = align_words(w + b.nrows[r]);
+        b.off[r] = w;
+        w = align_words(w + b.nrows[r] + 1);
+        b.ent[r] = w;
+        w = align_words(w + b.cap[r]);
     }
     b.total = w;
     return b;

@@ -59,6 +59,7 @@ extern "C" gale_status gale_build_static(gale_ctx *ctx, const int32_t *ids, int3
     if (ctx->cfg.mode != GALE_MODE_DIRECT) return fail(GALE_ESTATE, "gale_build_static is for DIRECT mode");
     gale_status s = check_request(ctx, ids, n, mask);
     if (s) return s;
+    if (mask & GALE_REL_EXT) return fail(GALE_EINVAL, "gale_build_static builds VT, VV and TT");
     {
         std::vector<int32_t> u(ids, ids + n);
         std::sort(u.begin(), u.end());

@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgale.so")
 
 REL_VT, REL_VV, REL_TT, REL_ALL = 1, 2, 4, 7
+REL_VE, REL_VF, REL_EF, REL_ET, REL_FT, REL_EXT = 8, 16, 32, 64, 128, 248
 FORM_PLAIN, FORM_BATCHED = 0, 1
 MODE_DIRECT, MODE_SERVE = 0, 1
 FRONT_SINGLE, FRONT_PER_RELATION = 0, 1
@@ -30,6 +31,7 @@ class GaleConfig(C.Structure):
         ("max_queue", C.c_int32), ("launch_classes", C.c_int32), ("hip_stream", C.c_void_p),
         ("global_cu_share", C.c_double), ("dev_arena", C.c_void_p), ("arena_bytes", C.c_uint64),
         ("tune_table_path", C.c_char_p), ("prefetch_depth", C.c_int32), ("front_end", C.c_int32),
+        ("simplex_lists", C.c_int32),
     ]
 
 
@@ -64,6 +66,14 @@ class GaleStats(C.Structure):
         ("wait_kernel_copy_s_max", C.c_double), ("wait_integration_s_max", C.c_double),
         ("prefetch_built", C.c_uint64), ("prefetch_hits", C.c_uint64), ("prefetch_evicted", C.c_uint64),
         ("demand_evictions", C.c_uint64), ("front_end", C.c_int32), ("tune_applied", C.c_int32),
+    ]
+
+
+class GaleSimplices(C.Structure):
+    _fields_ = [
+        ("ne", C.c_int64), ("nf", C.c_int64), ("ncl", C.c_int32), ("pad", C.c_int32),
+        ("e", C.POINTER(C.c_int32)), ("f", C.POINTER(C.c_int32)), ("ie", C.POINTER(C.c_int64)),
+        ("if_", C.POINTER(C.c_int64)),
     ]
 
 
@@ -132,6 +142,7 @@ def load_library(path: str = LIB_PATH):
         "gale_get_stats": ([vp, C.POINTER(GaleStats)], C.c_int32),
         "gale_reset_stats": ([vp], C.c_int32),
         "gale_get_cluster_info": ([vp, C.c_int32, C.POINTER(GaleClusterInfo)], C.c_int32),
+        "gale_get_simplices": ([vp, C.POINTER(GaleSimplices)], C.c_int32),
         "gale_stream": ([vp], vp),
         "gale_strerror": ([C.c_int32], C.c_char_p),
         "gale_last_error": ([], C.c_char_p),
@@ -170,7 +181,7 @@ class Context:
                  lds_bytes: int = 0, max_inflight: int = 0, cache_budget_bytes: int = 0, max_queue: int = 0,
                  stream=None, launch_classes: int = 0, global_cu_share: float = 0.0, dev_arena=None,
                  arena_bytes: int = 0, tune_table_path: str | None = None, prefetch_depth: int = 0,
-                 front_end: str = "single"):
+                 front_end: str = "single", simplex_lists: bool = False):
         lib = load_library()
         self._lib = lib
         cfg = GaleConfig()
@@ -191,6 +202,7 @@ class Context:
         cfg.tune_table_path = self._tune_path
         cfg.prefetch_depth = prefetch_depth
         cfg.front_end = {"single": FRONT_SINGLE, "per_relation": FRONT_PER_RELATION}[front_end]
+        cfg.simplex_lists = 1 if simplex_lists else 0
         h = C.c_void_p()
         _check(lib.gale_create(C.byref(cfg), C.byref(h)), "gale_create")
         self._h = h
@@ -323,6 +335,18 @@ class Context:
         _check(self._lib.gale_get_cluster_info(self._h, int(cluster), C.byref(ci)), "gale_get_cluster_info")
         return {name: getattr(ci, name) for name, _ in GaleClusterInfo._fields_}
 
+    def simplices(self):
+        """(E as ne x 2, I_E, F as nf x 3, I_F) copied from the library's
+        edge and triangle lists (gale_get_simplices)."""
+        x = GaleSimplices()
+        _check(self._lib.gale_get_simplices(self._h, C.byref(x)), "gale_get_simplices")
+        ne, nf, ncl = x.ne, x.nf, x.ncl
+        e = np.ctypeslib.as_array(x.e, shape=(2 * ne,)).reshape(ne, 2).copy() if ne else np.empty((0, 2), np.int32)
+        f = np.ctypeslib.as_array(x.f, shape=(3 * nf,)).reshape(nf, 3).copy() if nf else np.empty((0, 3), np.int32)
+        ie = np.ctypeslib.as_array(x.ie, shape=(ncl + 1,)).copy()
+        if_ = np.ctypeslib.as_array(x.if_, shape=(ncl + 1,)).copy()
+        return e, ie, f, if_
+
     def reset_stats(self):
         _check(self._lib.gale_reset_stats(self._h), "gale_reset_stats")
 
@@ -375,3 +399,4 @@ def consumer_run(ctx: "Context", tets, field, cluster_order, threads: int = 40, 
     if st != OK:
         raise GaleError(st, "gale_consumer_run", "bad argument")
     return {name: getattr(res, name) for name, _ in GaleConsumerResult._fields_ if not name.startswith("pad")}
+

@@ -279,10 +279,14 @@ def test_error_paths():
             ctx.load(bad, m.cluster, m.nclusters)
         assert ei.value.status == gale.EINVAL
         ctx.load(m.tets, m.cluster, m.nclusters)
-        for ids, mask in (([m.nclusters], 7), ([-1], 7), ([0], 0), ([0], 8)):
+        for ids, mask in (([m.nclusters], 7), ([-1], 7), ([0], 0), ([0], 256)):
             with pytest.raises(gale.GaleError) as ei:
                 ctx.submit(ids, mask)
             assert ei.value.status == gale.EINVAL
+        # an edge / triangle relation on a mesh loaded without the lists
+        with pytest.raises(gale.GaleError) as ei:
+            ctx.submit([0], 8)
+        assert ei.value.status == gale.ESTATE
         tk = ctx.submit([0, 1], 1)
         with pytest.raises(gale.GaleError) as ei:
             ctx.block(tk, 0, 2)
@@ -506,14 +510,15 @@ def test_face_table_overflow_doubles_passes(path, lds):
     """Loose tetrahedra (3,900 distinct faces for 1,000 TT rows) overflow the
     face table sized by the estimate of 2.5 faces per row at load 0.7: with
     these budgets the LDS plan starts with one pass over 3,750 cells and the
-    hybrid plan with two over 1,900, so a pass fills its table and the kernel
-    starts again with twice the passes.  The blocks still equal the oracle's
-    and no cluster needs exhaustive pairing."""
+    hybrid plan (bit 4 of launch_classes sends the cluster to the global path)
+    with two over 1,900, so a pass fills its table and the kernel starts again
+    with twice the passes.  The blocks still equal the oracle's and no cluster
+    needs exhaustive pairing."""
     gale = _gale()
     m = meshgen.loose_tets()
     orc = oracle.Oracle.of(m)
     _say("face table overflow", path, lds)
-    with gale.Context(form="batched", lds_bytes=lds) as ctx:
+    with gale.Context(form="batched", lds_bytes=lds, launch_classes=16 if path == "hybrid" else 0) as ctx:
         ctx.load(m.tets, m.cluster, m.nclusters)
         compare_all(ctx, m, orc, mask=4)
         st = ctx.stats()

@@ -1,0 +1,181 @@
+"""GPU parity of the edge and triangle relations: the library's lists E, F
+and interval arrays equal the oracle's, and every VE, VF, EF, ET and FT block
+built on the GPU equals the oracle's byte for byte (integer data, tolerance 0),
+through the C ABI, in the plain and batched forms, alone and mixed with VT,
+VV and TT in one request."""
+import sys
+
+import numpy as np
+import pytest
+
+import meshgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+EXT = (8, 16, 32, 64, 128)
+
+
+def _gale():
+    from paper_2507_15230_amd import gale
+    return gale
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _compare(ctx, orc, ids, mask, form="batched"):
+    gale = _gale()
+    ids = np.asarray(ids, np.int32)
+    tk = ctx.submit(ids, mask) if form is None else None
+    if tk is None:
+        tk = ctx.submit(ids, mask)
+    bad = []
+    rels = [r for r in (1, 2, 4) + EXT if mask & r]
+    pairs = [(int(k), r) for k in np.unique(ids) for r in rels]
+    exp = orc.blocks(pairs)
+    for (k, r), e in zip(pairs, exp):
+        got = ctx.block(tk, k, r)
+        if not all(g.shape == x.shape and np.array_equal(g, x) for g, x in zip(got, e)):
+            bad.append((k, r))
+    ctx.release(tk)
+    assert gale is not None
+    return bad
+
+
+def _lists_equal(ctx, orc):
+    e, ie, f, if_ = ctx.simplices()
+    oe, oie, of, oif = orc.simplices()
+    return (np.array_equal(e, oe) and np.array_equal(ie, oie) and np.array_equal(f, of)
+            and np.array_equal(if_, oif))
+
+
+SMALL = {
+    "cube": meshgen.cube(),
+    "cube_z": meshgen.cube([0, 0, 0, 0, 1, 1, 1, 1]),
+    "fig4": meshgen.fig4_example(),
+    "single": meshgen.single_tet(),
+    "rand1": meshgen.random_small(1, n=5, nclusters=6, drop=0.5, isolated=4, empty_clusters=3),
+    "rand2": meshgen.random_small(2, n=6, nclusters=9, drop=0.2),
+    "grid6": meshgen.grid_mesh(6, 30, seed=4),
+    "nonmanifold": meshgen.nonmanifold(n=6, fins=8, dups=4, nclusters=3, seed=3),
+}
+
+
+@pytest.mark.parametrize("form", ["plain", "batched"])
+@pytest.mark.parametrize("name", sorted(SMALL))
+def test_small_cases(name, form):
+    gale = _gale()
+    m = SMALL[name]
+    orc = oracle.Oracle.of(m)
+    with gale.Context(form=form, simplex_lists=True) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        assert _lists_equal(ctx, orc)
+        ids = np.arange(m.nclusters, dtype=np.int32)
+        assert not _compare(ctx, orc, ids, gale.REL_EXT)
+        assert not _compare(ctx, orc, ids, 255)
+
+
+def test_section44_example_lists():
+    """The library numbers the example mesh's edges and triangles as the
+    paper prints them (Section 4.4): I_E = 0, 9, 12; f5 = v0 v3 v4 with edges
+    e2, e6, e9."""
+    gale = _gale()
+    m = meshgen.fig4_example()
+    with gale.Context(simplex_lists=True) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        e, ie, f, _ = ctx.simplices()
+    assert list(ie) == [0, 9, 12] and list(f[5]) == [0, 3, 4]
+    ids = {tuple(x): i for i, x in enumerate(e.tolist())}
+    assert sorted([ids[(0, 3)], ids[(0, 4)], ids[(3, 4)]]) == [2, 6, 9]
+
+
+@pytest.mark.parametrize("mask", [8, 16, 32, 64, 128, 8 | 64, 16 | 32 | 128, 1 | 16, 2 | 8 | 4 | 128])
+def test_masks_on_refined_mesh(mask):
+    """A refined lognormal mesh (vertex valences up to ~100, rows longer than
+    a wave sort's short path), each relation alone and in combinations."""
+    gale = _gale()
+    m = meshgen.refined_mesh(16, 0.08, 2, 128, 1.0, seed=5)
+    orc = oracle.Oracle.of(m)
+    with gale.Context(simplex_lists=True) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        ids = np.arange(m.nclusters, dtype=np.int32)
+        bad = _compare(ctx, orc, ids, mask)
+    assert not bad, bad[:10]
+
+
+def test_high_valence_fans():
+    """Closed fans with vertices in up to 1,040 tetrahedra: VE and VF rows
+    sorted by the per-wave bitonic network and rank sort."""
+    gale = _gale()
+    m = meshgen.fans(seed=11)
+    orc = oracle.Oracle.of(m)
+    with gale.Context(simplex_lists=True) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        bad = _compare(ctx, orc, np.arange(m.nclusters, dtype=np.int32), gale.REL_EXT)
+    assert not bad, bad[:10]
+
+
+def test_config1_every_block_and_sums():
+    """32^3 lattice: the lists equal the oracle's, every block of every
+    cluster too, and the sums match the incidence counts of the lattice
+    (sum VE = 2E, sum VF = sum EF = 3F, sum ET = 6T, sum FT = 4T)."""
+    gale = _gale()
+    m = meshgen.config(1)
+    orc = oracle.Oracle.of(m)
+    with gale.Context(form="batched", simplex_lists=True) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        assert _lists_equal(ctx, orc)
+        ids = np.arange(m.nclusters, dtype=np.int32)
+        e0 = ctx.stats()["entries_built"]
+        assert not _compare(ctx, orc, ids, gale.REL_EXT)
+        built = ctx.stats()["entries_built"] - e0
+    E, T = 217279, 178746
+    F = 1 - 32 ** 3 + E + T
+    assert built == 2 * E + 3 * F + 3 * F + 6 * T + 4 * T
+
+
+def test_config2_sampled():
+    """128^3 lattice (12.3M tetrahedra): lists equal the oracle's; a seeded
+    5 % sample of the clusters plus the first and last, every relation."""
+    gale = _gale()
+    m = meshgen.config(2)
+    orc = oracle.Oracle.of(m)
+    _say("config 2: enumerating")
+    with gale.Context(form="batched", simplex_lists=True) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        _say("loaded in %.1f s" % ctx.stats()["load_seconds"])
+        assert _lists_equal(ctx, orc)
+        rng = np.random.default_rng(7)
+        ids = np.unique(np.concatenate([rng.choice(m.nclusters, m.nclusters // 20, replace=False),
+                                        [0, m.nclusters - 1]])).astype(np.int32)
+        bad = _compare(ctx, orc, ids, gale.REL_EXT)
+    assert not bad, bad[:10]
+
+
+def test_errors():
+    gale = _gale()
+    m = meshgen.grid_mesh(6, 30, seed=4)
+    with gale.Context() as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        with pytest.raises(gale.GaleError) as e:
+            ctx.submit([0], gale.REL_VE)
+        assert e.value.status == gale.ESTATE
+        with pytest.raises(gale.GaleError) as e:
+            ctx.simplices()
+        assert e.value.status == gale.ESTATE
+    with gale.Context(simplex_lists=True) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        with pytest.raises(gale.GaleError) as e:
+            ctx.submit([0], 256)
+        assert e.value.status == gale.EINVAL
+        with pytest.raises(gale.GaleError) as e:
+            ctx.graph_create([0], gale.REL_VE)
+        assert e.value.status == gale.EINVAL
+        tk = ctx.submit([0], gale.REL_VE)
+        with pytest.raises(gale.GaleError) as e:
+            ctx.block(tk, 0, gale.REL_VT)
+        assert e.value.status == gale.ENOENT
+        ctx.release(tk)
