@@ -99,6 +99,23 @@ class GaleConsumerResult(C.Structure):
     ]
 
 
+class GaleGradientCfg(C.Structure):
+    _fields_ = [
+        ("threads", C.c_int32), ("n_order", C.c_int32), ("cluster_order", C.POINTER(C.c_int32)),
+        ("tets", C.POINTER(C.c_int32)), ("nt", C.c_int64), ("field", C.POINTER(C.c_float)),
+        ("nv", C.c_int32), ("pad", C.c_int32),
+    ]
+
+
+class GaleGradientResult(C.Structure):
+    _fields_ = [
+        ("clusters", C.c_uint64), ("errors", C.c_uint64), ("critical", C.c_uint64 * 4), ("pairs", C.c_uint64 * 3),
+        ("wall_s", C.c_double), ("lat_p50_us", C.c_double), ("lat_p99_us", C.c_double),
+        ("lat_mean_us", C.c_double), ("lat_max_us", C.c_double), ("request_s_max", C.c_double),
+        ("compute_s_max", C.c_double), ("first_error", C.c_int32), ("pad", C.c_int32),
+    ]
+
+
 class GaleError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         super().__init__("%s: %s (%s) %s" % (where, _NAMES.get(status, status), status, detail))
@@ -154,6 +171,10 @@ def load_library(path: str = LIB_PATH):
         "gale_lowerstar_classify": ([C.c_int32, i32p, i32p, i32p, i32p, i32p, i32p, C.c_int64,
                                      C.POINTER(C.c_float), C.c_int32, i32p], C.c_int32),
         "gale_consumer_run": ([vp, C.POINTER(GaleConsumerCfg), C.POINTER(GaleConsumerResult)], C.c_int32),
+        "gale_gradient_cluster": ([C.c_int32, i32p, i32p, i32p, i32p, i32p, i32p, i32p, i32p, C.c_int64, i32p,
+                                   C.c_int64, i32p, C.c_int64, C.POINTER(C.c_float), C.c_int32, i32p, C.c_int64,
+                                   C.POINTER(C.c_int64)], C.c_int32),
+        "gale_gradient_run": ([vp, C.POINTER(GaleGradientCfg), C.POINTER(GaleGradientResult)], C.c_int32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -400,3 +421,50 @@ def consumer_run(ctx: "Context", tets, field, cluster_order, threads: int = 40, 
         raise GaleError(st, "gale_consumer_run", "bad argument")
     return {name: getattr(res, name) for name, _ in GaleConsumerResult._fields_ if not name.startswith("pad")}
 
+
+def gradient_cluster(ve, vf, vt, edges, faces, tets, field) -> np.ndarray:
+    """Discrete gradient of one cluster's lower stars (include/gale_gradient.h)
+    from its VE, VF, VT blocks (each (row_ids, offsets, entries)), the edge and
+    triangle lists, the mesh and a float32 field; returns the records as an
+    (n, 3) int32 array of {dim, lower id, upper id} (upper -1: critical)."""
+    lib = load_library()
+    i32 = C.POINTER(C.c_int32)
+    rows = np.ascontiguousarray(ve[0], np.int32)
+    arrs = [np.ascontiguousarray(a, np.int32) for a in (ve[1], ve[2], vf[1], vf[2], vt[1], vt[2])]
+    edges = np.ascontiguousarray(edges, np.int32).reshape(-1)
+    faces = np.ascontiguousarray(faces, np.int32).reshape(-1)
+    tets = np.ascontiguousarray(tets, np.int32).reshape(-1)
+    field = np.ascontiguousarray(field, np.float32)
+    cap = rows.shape[0] + arrs[1].shape[0] + arrs[3].shape[0] + arrs[5].shape[0]
+    rec = np.empty((max(cap, 1), 3), np.int32)
+    n = C.c_int64()
+    p = [a.ctypes.data_as(i32) for a in arrs]
+    st = lib.gale_gradient_cluster(int(rows.shape[0]), rows.ctypes.data_as(i32), p[0], p[1], p[2], p[3], p[4], p[5],
+                                   edges.ctypes.data_as(i32), int(edges.shape[0] // 2), faces.ctypes.data_as(i32),
+                                   int(faces.shape[0] // 3), tets.ctypes.data_as(i32), int(tets.shape[0] // 4),
+                                   field.ctypes.data_as(C.POINTER(C.c_float)), int(field.shape[0]),
+                                   rec.ctypes.data_as(i32), int(cap), C.byref(n))
+    if st != 0:
+        raise GaleError(EINVAL, "gale_gradient_cluster", "invalid block, id out of range or record space")
+    return rec[: n.value].copy()
+
+
+def gradient_run(ctx: "Context", tets, field, cluster_order, threads: int = 40) -> dict:
+    """The DiscreteGradient workload with native threads against a DIRECT-mode
+    context loaded with simplex_lists (include/gale_gradient.h)."""
+    lib = load_library()
+    order = np.ascontiguousarray(cluster_order, np.int32)
+    tets = np.ascontiguousarray(tets, np.int32)
+    field = np.ascontiguousarray(field, np.float32)
+    i32 = C.POINTER(C.c_int32)
+    cfg = GaleGradientCfg(threads=int(threads), n_order=int(order.shape[0]), cluster_order=order.ctypes.data_as(i32),
+                          tets=tets.ctypes.data_as(i32), nt=int(tets.shape[0]),
+                          field=field.ctypes.data_as(C.POINTER(C.c_float)), nv=int(field.shape[0]))
+    res = GaleGradientResult()
+    st = lib.gale_gradient_run(ctx._h, C.byref(cfg), C.byref(res))
+    if st != OK:
+        raise GaleError(st, "gale_gradient_run", "bad argument or context")
+    out = {name: getattr(res, name) for name, _ in GaleGradientResult._fields_ if not name.startswith("pad")}
+    out["critical"] = list(res.critical)
+    out["pairs"] = list(res.pairs)
+    return out
