@@ -305,6 +305,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--block-threads", type=int, default=1024)
+    ap.add_argument("--tile-entries", type=int, default=0,
+                    help="VT entries per tile of clusters too large for LDS (0 = the library default, < 0 = no tiles)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -366,7 +368,7 @@ def main():
         del src, dst
 
     ctx = gale.Context(device=0, mode="direct", form="batched", block_threads=args.block_threads,
-                       stream=stream.cuda_stream, tune_table_path=args.tune_table)
+                       stream=stream.cuda_stream, tune_table_path=args.tune_table, tile_entries=args.tile_entries)
     log("loading")
     ctx.load(mesh.tets, mesh.cluster, ncl)
     st0 = ctx.stats()
@@ -502,6 +504,7 @@ def main():
             "load_seconds": st0["load_seconds"],
             "global_path_blocks_per_step": int(st["global_path_blocks"] // max(1, st["requests"])),
             "hybrid_path_blocks_per_step": int(st["hybrid_path_blocks"] // max(1, st["requests"])),
+            "tile_entries": args.tile_entries,
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -131,6 +131,11 @@ typedef struct {
                                      their interval arrays (Section 4.3: built only when an algorithm needs edge
                                      or triangle relations), which the VE, VF, EF, ET and FT relations and
                                      gale_get_simplices need */
+    int32_t  tile_entries;        /* DIRECT mode, BATCHED form: a cluster whose working set does not fit the LDS of
+                                     a 1024-thread workgroup is built as tiles of about this many VT entries (its
+                                     vertices split in breadth-first layers), each on the LDS path like a cluster
+                                     of its own, then assembled into the cluster's block; 0 = 10000, < 0 = never
+                                     (such clusters then run on the global-memory path) */
 } gale_config;
 
 #define GALE_FRONT_SINGLE       0

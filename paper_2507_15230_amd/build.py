@@ -17,7 +17,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgale.so")
 
 SOURCES = ["gale_kernels.hip", "gale_load.cpp", "gale_api.cpp", "gale_serve.cpp", "gale_lowerstar.cpp", "gale_static.cpp",
-           "gale_simplices.cpp", "gale_cobound.hip", "gale_gradient.cpp"]
+           "gale_simplices.cpp", "gale_cobound.hip", "gale_gradient.cpp",
+           "gale_tiles.cpp", "gale_stitch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

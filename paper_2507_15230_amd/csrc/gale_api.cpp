@@ -428,26 +428,115 @@ gale_status launch_ext_items(gale_ctx *ctx, Batch &b, int form, const std::vecto
     return GALE_OK;
 }
 
+// Batched form, DIRECT mode: the VT / VV / TT items of tiled clusters are
+// replaced in `base` by one item per tile, whose blocks are laid out from
+// word `words` on (header slots from `nh` on); `stitch` receives the
+// clusters to assemble and `tiles` the tile items in stitch order.
+void expand_tiles(const gale_ctx *ctx, std::vector<WorkItem> &base, int64_t &words, int &nh,
+                  std::vector<StitchItem> &stitch, std::vector<WorkItem> &tiles) {
+    if (ctx->ntiles == 0) return;
+    std::vector<WorkItem> out;
+    out.reserve(base.size());
+    for (const WorkItem &it : base) {
+        const int32_t c = it.cluster;
+        if (c >= ctx->ncl || ctx->tile_count[c] == 0) {
+            out.push_back(it);
+            continue;
+        }
+        StitchItem si{};
+        si.out_word = it.out_word;
+        si.cluster = c;
+        si.mask = it.mask;
+        si.cap_vv = it.cap_vv;
+        si.cap_tt = it.cap_tt;
+        si.hdr_index = it.hdr_index;
+        si.tiles = (int32_t)tiles.size();
+        stitch.push_back(si);
+        for (int32_t j = 0; j < ctx->tile_count[c]; ++j) {
+            WorkItem ti{};
+            ti.cluster = ctx->ncl + ctx->tile_first[c] + j;
+            ti.mask = it.mask;
+            const ClusterMeta &m = ctx->meta[ti.cluster];
+            ti.cap_vv = (it.mask & kRelVV) ? m.cap_vv : 0;
+            ti.cap_tt = (it.mask & kRelTT) ? default_cap_tt(m) : 0;
+            ti.out_word = words;
+            ti.hdr_index = nh++;
+            words += block_layout(ti.mask, m.nV, m.nT, m.nnzVT, ti.cap_vv, ti.cap_tt).total;
+            tiles.push_back(ti);
+            out.push_back(ti);
+        }
+    }
+    base.swap(out);
+}
+
+// The stitch launch over `stitch` (after the tiles' launches on st): work
+// list = queue word, stitch items, tile items; into the batch's buffers.
+gale_status launch_stitch_items(gale_ctx *ctx, Batch &b, const std::vector<StitchItem> &stitch,
+                                const std::vector<WorkItem> &tiles, hipStream_t st, bool upload) {
+    hipError_t e = hipSuccess;
+    const int ns = (int)stitch.size();
+    if (ns == 0) return GALE_OK;
+    const size_t bytes = 64 + (size_t)ns * sizeof(StitchItem) + tiles.size() * sizeof(WorkItem);
+    if (upload) {
+        b.st_items = ctx->dev_pool.acquire(bytes, &e);
+        b.st_host = ctx->pin_pool.acquire(bytes, &e);
+        if (!b.st_items || !b.st_host) return fail(GALE_ENOMEM, "stitch work list");
+        char *h = (char *)b.st_host->ptr;
+        std::memset(h, 0, 64);
+        std::memcpy(h + 64, stitch.data(), (size_t)ns * sizeof(StitchItem));
+        std::memcpy(h + 64 + (size_t)ns * sizeof(StitchItem), tiles.data(), tiles.size() * sizeof(WorkItem));
+        e = hipMemcpyAsync(b.st_items->ptr, h, bytes, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return fail(GALE_EDEVICE, std::string("stitch list copy: ") + hipGetErrorString(e));
+    }
+    char *d = (char *)b.st_items->ptr;
+    SArgs a{};
+    a.meta = ctx->d_meta;
+    a.sm = ctx->d_sm;
+    a.maps = ctx->d_maps;
+    a.out = (int32_t *)b.out->ptr;
+    a.hdr = (int32_t *)b.dev_hdr->ptr;
+    a.items = (const StitchItem *)(d + 64);
+    a.tiles = (const WorkItem *)(d + 64 + (size_t)ns * sizeof(StitchItem));
+    a.nitems = ns;
+    a.queue = (int32_t *)d;
+    const int grid = std::max(1, std::min(ns, ctx->num_cus * 4));
+    e = launch_stitch(a, grid, st);
+    ctx->n_launches++;
+    if (e != hipSuccess) return fail(GALE_EDEVICE, std::string("stitch launch: ") + hipGetErrorString(e));
+    return GALE_OK;
+}
+
 // Lay out the batch's items in a fresh output buffer and launch them.
 gale_status run_items(gale_ctx *ctx, Batch &b, int form, hipStream_t st) {
     hipError_t e;
     const int n = (int)b.items.size();
     b.out_words = lay_out_items(ctx, b.items, 0);
-    b.out = ctx->dev_pool.acquire((size_t)b.out_words * 4 + 256, &e);
+    std::vector<WorkItem> base, ext, tiles;
+    std::vector<StitchItem> stitch;
+    for (const WorkItem &it : b.items) ((it.mask & kRelExt) ? ext : base).push_back(it);
+    int64_t words = b.out_words;
+    int nh = n;
+    if (form == GALE_FORM_BATCHED && ctx->cfg.mode == GALE_MODE_DIRECT)
+        expand_tiles(ctx, base, words, nh, stitch, tiles);
+    b.out = ctx->dev_pool.acquire((size_t)words * 4 + 256, &e);
     if (!b.out) return fail(GALE_ENOMEM, "device output buffer");
     b.host_hdr = ctx->pin_pool.acquire((size_t)n * 32 + 64, &e);
     if (!b.host_hdr) return fail(GALE_ENOMEM, "batch buffers");
     if (n == 0) return GALE_OK;
-    std::vector<WorkItem> base, ext;
-    for (const WorkItem &it : b.items) ((it.mask & kRelExt) ? ext : base).push_back(it);
-    if (!ext.empty()) {
-        b.dev_hdr = ctx->dev_pool.acquire((size_t)n * 32 + 64, &e);
+    if (!ext.empty() || nh > n) {
+        b.dev_hdr = ctx->dev_pool.acquire((size_t)nh * 32 + 64, &e);
         if (!b.dev_hdr) return fail(GALE_ENOMEM, "batch buffers");
     }
     gale_status s = GALE_OK;
     if (!base.empty())
         s = upload_and_launch(ctx, form, base, (int32_t *)b.out->ptr, b.dev_items, b.dev_hdr, b.host_items, b.ws, st,
                               b.kev[0] ? b.kev : nullptr, &b.kev_recorded);
+    if (!s && !stitch.empty()) {
+        s = launch_stitch_items(ctx, b, stitch, tiles, st, true);
+        // the kernel-time events bracket the stitch too
+        if (!s && b.kev[1] && hipEventRecord(b.kev[1], st) != hipSuccess)
+            s = fail(GALE_EDEVICE, "event record");
+    }
     if (!s) s = launch_ext_items(ctx, b, form, ext, st);
     return s;
 }
@@ -460,7 +549,9 @@ void release_batch(gale_ctx *ctx, Batch &b) {
     ctx->dev_pool.release(b.ext_items);
     ctx->dev_pool.release(b.ext_ws);
     ctx->pin_pool.release(b.ext_host);
-    b.ext_items = b.ext_ws = b.ext_host = nullptr;
+    ctx->dev_pool.release(b.st_items);
+    ctx->pin_pool.release(b.st_host);
+    b.ext_items = b.ext_ws = b.ext_host = b.st_items = b.st_host = nullptr;
     ctx->dev_pool.release(b.out);
     ctx->dev_pool.release(b.dev_items);
     ctx->dev_pool.release(b.dev_hdr);
@@ -862,27 +953,52 @@ gale_status graph_create(gale_ctx *ctx, const int32_t *ids, int32_t n, uint32_t 
     hipError_t e = hipSuccess;
     const int ni = (int)b.items.size();
     b.out_words = lay_out_items(ctx, b.items, 0);
-    b.out = ctx->dev_pool.acquire((size_t)b.out_words * 4 + 256, &e);
+    // tiled clusters: their tiles' items launched, the stitch captured after
+    std::vector<WorkItem> launch(b.items), tiles;
+    std::vector<StitchItem> stitch;
+    int64_t words = b.out_words;
+    int nh = ni;
+    expand_tiles(ctx, launch, words, nh, stitch, tiles);
+    b.out = ctx->dev_pool.acquire((size_t)words * 4 + 256, &e);
     b.host_hdr = ctx->pin_pool.acquire((size_t)ni * 32 + 64, &e);
-    if (!b.out || !b.host_hdr) s = fail(GALE_ENOMEM, "prepared request buffers");
+    if (nh > ni) b.dev_hdr = ctx->dev_pool.acquire((size_t)nh * 32 + 64, &e);
+    if (!b.out || !b.host_hdr || (nh > ni && !b.dev_hdr)) s = fail(GALE_ENOMEM, "prepared request buffers");
     std::vector<int> ncls;
     int n_glob = 0;
     int64_t wsb = 0;
     if (!s && ni > 0)
-        s = stage_items(ctx, GALE_FORM_BATCHED, b.items, b.dev_items, b.dev_hdr, b.host_items, b.ws, ctx->stream,
+        s = stage_items(ctx, GALE_FORM_BATCHED, launch, b.dev_items, b.dev_hdr, b.host_items, b.ws, ctx->stream,
                         ncls, n_glob, wsb);
+    if (!s && !stitch.empty()) {
+        // the stitch work list goes up now; the capture only zeroes its queue word
+        b.st_items = ctx->dev_pool.acquire(64 + stitch.size() * sizeof(StitchItem) + tiles.size() * sizeof(WorkItem), &e);
+        b.st_host = ctx->pin_pool.acquire(64 + stitch.size() * sizeof(StitchItem) + tiles.size() * sizeof(WorkItem), &e);
+        if (!b.st_items || !b.st_host) s = fail(GALE_ENOMEM, "stitch work list");
+        if (!s) {
+            char *h = (char *)b.st_host->ptr;
+            std::memset(h, 0, 64);
+            std::memcpy(h + 64, stitch.data(), stitch.size() * sizeof(StitchItem));
+            std::memcpy(h + 64 + stitch.size() * sizeof(StitchItem), tiles.data(), tiles.size() * sizeof(WorkItem));
+            if (hipMemcpyAsync(b.st_items->ptr, h, 64 + stitch.size() * sizeof(StitchItem) +
+                                                      tiles.size() * sizeof(WorkItem),
+                               hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+                s = fail(GALE_EDEVICE, "stitch list copy");
+        }
+    }
     if (!s && hipStreamSynchronize(ctx->stream) != hipSuccess) s = fail(GALE_EDEVICE, "work list copy");
     if (!s && ni > 0) {
         // capture: zero the queue words, then the launches (forked over the
-        // auxiliary streams and joined back)
+        // auxiliary streams and joined back), then the stitch
         e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) e = launch_zero((int32_t *)b.dev_items->ptr, 16, ctx->stream);
+        if (e == hipSuccess && b.st_items) e = launch_zero((int32_t *)b.st_items->ptr, 16, ctx->stream);
         gale_status ls = GALE_OK;
         if (e == hipSuccess) {
             char *di = (char *)b.dev_items->ptr;
             ls = launch_batch(ctx, GALE_FORM_BATCHED, (int32_t *)b.out->ptr, (int32_t *)b.dev_hdr->ptr,
                               (const WorkItem *)(di + 64), ncls, n_glob, (int32_t *)di,
                               b.ws ? (char *)b.ws->ptr : nullptr, wsb, ctx->stream, true, nullptr, nullptr);
+            if (ls == GALE_OK && !stitch.empty()) ls = launch_stitch_items(ctx, b, stitch, tiles, ctx->stream, false);
         }
         hipGraph_t graph = nullptr;
         const hipError_t e2 = hipStreamEndCapture(ctx->stream, &graph);
@@ -1138,6 +1254,58 @@ gale_status gale_load(gale_ctx *ctx, int32_t nv, int64_t nt, const int32_t *tv, 
     std::string err;
     gale_status s = prepare_streams(nv, nt, tv, cl, ncl, hs, err);
     if (s) return fail(s, err);
+    // tiles of the clusters that do not fit a 1024-thread workgroup's LDS
+    // (DIRECT mode): their streams are prepared as pseudo-clusters and
+    // appended after the clusters' own, their metadata after the clusters'
+    std::vector<StitchMeta> smeta;
+    std::vector<int32_t> smaps;
+    if (ctx->cfg.mode == GALE_MODE_DIRECT && ctx->cfg.tile_entries >= 0) {
+        const int64_t tile_vt = ctx->cfg.tile_entries > 0 ? ctx->cfg.tile_entries : 10000;
+        std::vector<ClusterMeta> want(hs.meta);
+        for (ClusterMeta &m : want)
+            if (lds_plan(m, kRelBase, ctx->lds_budget, 1024).ok) m.nnzVT = 0;  // fits: not tiled
+        TilePlan tp;
+        s = plan_tiles(nv, nt, tv, cl, ncl, want, tile_vt, tp);
+        if (s) return fail(s, "tile plan");
+        if (tp.ntiles > 0) {
+            HostStreams ts;
+            s = prepare_streams(nv, nt, tv, tp.pseudo.data(), tp.npseudo, ts, err, &tp.keep);
+            if (s) return fail(s, err);
+            stitch_maps(tp, ts, ncl, smeta, smaps);
+            const int64_t tb0 = (int64_t)hs.tets.size(), tid0 = (int64_t)hs.tid.size(),
+                          lv0 = (int64_t)hs.lverts.size();
+            int64_t tbn = 0, tidn = 0, lvn = 0;
+            for (int32_t i = 0; i < tp.ntiles; ++i) {
+                const ClusterMeta &m = ts.meta[tp.pseudo_of_tile[i]];
+                const int64_t ntot = (int64_t)m.ns + m.nh;
+                tbn += (ntot * ((m.flags & kMetaWide) ? 16 : 8) + 15) / 16 * 16;
+                tidn += ntot;
+                lvn += m.L;
+            }
+            hs.tets.resize((size_t)(tb0 + tbn));
+            hs.tid.resize((size_t)(tid0 + tidn));
+            hs.lverts.resize((size_t)(lv0 + lvn));
+            int64_t tb = tb0, ti = tid0, lv = lv0;
+            for (int32_t i = 0; i < tp.ntiles; ++i) {
+                ClusterMeta m = ts.meta[tp.pseudo_of_tile[i]];
+                const int64_t ntot = (int64_t)m.ns + m.nh;
+                const int64_t tbytes = (ntot * ((m.flags & kMetaWide) ? 16 : 8) + 15) / 16 * 16;
+                std::memcpy(hs.tets.data() + tb, ts.tets.data() + m.tb_off, (size_t)tbytes);
+                std::memcpy(hs.tid.data() + ti, ts.tid.data() + m.tet_off, (size_t)ntot * 4);
+                std::memcpy(hs.lverts.data() + lv, ts.lverts.data() + m.lv_off, (size_t)m.L * 4);
+                m.tb_off = tb;
+                m.tet_off = ti;
+                m.lv_off = lv;
+                tb += tbytes;
+                ti += ntot;
+                lv += m.L;
+                hs.meta.push_back(m);
+            }
+            ctx->ntiles = tp.ntiles;
+            ctx->tile_first = tp.tile_first;
+            ctx->tile_count = tp.tile_count;
+        }
+    }
     hipError_t e = hipSetDevice(ctx->cfg.device);
     auto up = [&](void **dst, const void *src, size_t bytes) -> hipError_t {
         hipError_t r = hipMalloc(dst, std::max<size_t>(bytes, 16));
@@ -1149,6 +1317,10 @@ gale_status gale_load(gale_ctx *ctx, int32_t nv, int64_t nt, const int32_t *tv, 
     if (e == hipSuccess) e = up((void **)&ctx->d_tid, hs.tid.data(), hs.tid.size() * 4);
     if (e == hipSuccess) e = up((void **)&ctx->d_lverts, hs.lverts.data(), hs.lverts.size() * 4);
     if (e == hipSuccess) e = up((void **)&ctx->d_meta, hs.meta.data(), hs.meta.size() * sizeof(ClusterMeta));
+    if (e == hipSuccess && ctx->ntiles > 0) {
+        e = up((void **)&ctx->d_sm, smeta.data(), smeta.size() * sizeof(StitchMeta));
+        if (e == hipSuccess) e = up((void **)&ctx->d_maps, smaps.data(), smaps.size() * 4);
+    }
     if (e != hipSuccess) {
         ctx->poisoned = true;
         return fail(e == hipErrorOutOfMemory ? GALE_ENOMEM : GALE_EDEVICE,
@@ -1532,6 +1704,8 @@ void gale_destroy(gale_ctx *ctx) {
     if (ctx->d_tid) (void)hipFree(ctx->d_tid);
     if (ctx->d_lverts) (void)hipFree(ctx->d_lverts);
     if (ctx->d_meta) (void)hipFree(ctx->d_meta);
+    if (ctx->d_sm) (void)hipFree(ctx->d_sm);
+    if (ctx->d_maps) (void)hipFree(ctx->d_maps);
     for (void *p : {(void *)ctx->d_ext, (void *)ctx->d_eoff, (void *)ctx->d_eidx, (void *)ctx->d_foff,
                     (void *)ctx->d_fidx})
         if (p) (void)hipFree(p);

@@ -58,6 +58,8 @@ struct Batch {
     bool borrowed = false;  // buffers owned by a prepared (graph) request, not by this batch
     // edge / triangle relation items (their own work list and workspace)
     Buf *ext_items = nullptr, *ext_host = nullptr, *ext_ws = nullptr;
+    // stitch of tiled clusters (work list: queue word, stitch items, tile items)
+    Buf *st_items = nullptr, *st_host = nullptr;
 };
 
 struct Ticket {
@@ -227,6 +229,13 @@ struct gale_ctx {
     uint8_t *d_tets = nullptr;
     int32_t *d_tid = nullptr, *d_lverts = nullptr;
     gale::ClusterMeta *d_meta = nullptr;
+    // tiles of large clusters (batched form): metadata entries ncl ..
+    // ncl + ntiles - 1 of meta / d_meta are tiles; per cluster its first tile
+    // and count (0: not tiled), the stitch metadata and maps on the device
+    int32_t ntiles = 0;
+    std::vector<int32_t> tile_first, tile_count;
+    gale::StitchMeta *d_sm = nullptr;
+    int32_t *d_maps = nullptr;
     // edge and triangle lists (gale_config.simplex_lists): host copies of E,
     // F and the interval arrays, the per-cluster ranges, and the device index
     bool has_simplices = false;

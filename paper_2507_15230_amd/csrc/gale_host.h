@@ -35,8 +35,24 @@ struct HostSimplices {
 
 gale_status enumerate_simplices(const HostStreams &hs, HostSimplices &out, std::string &err);
 
+// Tiles of large clusters (gale_tiles.cpp): pseudo-cluster of every vertex,
+// which pseudo-clusters are tiles, and per cluster its first tile and count.
+struct TilePlan {
+    int32_t ntiles = 0, npseudo = 0;
+    std::vector<int32_t> pseudo;          // nv
+    std::vector<char> keep;               // npseudo: a tile
+    std::vector<int32_t> tile_first, tile_count;  // ncl
+    std::vector<int32_t> pseudo_of_tile;  // ntiles
+};
+gale_status plan_tiles(int32_t nv, int64_t nt, const int32_t *tv, const int32_t *cl, int32_t ncl,
+                       const std::vector<ClusterMeta> &meta, int64_t tile_vt, TilePlan &tp);
+void stitch_maps(const TilePlan &tp, const HostStreams &ts, int32_t ncl, std::vector<StitchMeta> &sm,
+                 std::vector<int32_t> &maps);
+
+// keep (optional, ncl flags): build the local tables and streams of the
+// flagged clusters only; the others get empty streams and zero metadata
 gale_status prepare_streams(int32_t nv, int64_t nt, const int32_t *tv, const int32_t *cl, int32_t ncl,
-                            HostStreams &out, std::string &err);
+                            HostStreams &out, std::string &err, const std::vector<char> *keep = nullptr);
 
 struct KArgs;
 hipError_t launch_items(const KArgs &a, bool lds_path, int block_threads, int grid, size_t lds, hipStream_t st);
@@ -51,5 +67,8 @@ hipError_t persistent_occupancy(int block_threads, bool lds_path, size_t lds, in
 hipError_t launch_ext(const KArgs &a, int grid, hipStream_t st);
 int64_t ext_workspace_bytes(const ClusterMeta &m, const ExtMeta &x, uint32_t mask);
 constexpr int kExtThreads = 512;
+// the stitch of tiled clusters (persistent over a.items)
+hipError_t launch_stitch(const SArgs &a, int grid, hipStream_t st);
+constexpr int kStitchThreads = 256;
 
 }  // namespace gale

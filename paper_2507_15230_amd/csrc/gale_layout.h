@@ -133,6 +133,44 @@ struct Streams {
     const ClusterMeta *meta;
 };
 
+// A cluster built as tiles (batched form): its tiles are metadata entries
+// tile_first .. tile_first + ntiles - 1 past the clusters' own; the map
+// array holds, from vmap_off, (tile, row in the tile's block) for each of
+// its nv vertices in ascending id, and from tmap_off the same for each of its
+// nt internal tetrahedra.
+constexpr int kMaxTilesPerCluster = 64;
+struct StitchMeta {
+    int64_t vmap_off, tmap_off;
+    int32_t tile_first, ntiles, nv, nt;
+};
+static_assert(sizeof(StitchMeta) == 32, "StitchMeta layout");
+
+// One tiled cluster to assemble: its block (out_word, capacities, header
+// slot) and the position of its tiles' work items in the stitch launch's
+// tile table.
+struct StitchItem {
+    int64_t out_word;
+    int32_t cluster;
+    uint32_t mask;
+    int32_t cap_vv, cap_tt;
+    int32_t hdr_index;
+    int32_t tiles;
+};
+static_assert(sizeof(StitchItem) == 32, "StitchItem layout");
+
+struct SArgs {
+    const ClusterMeta *meta;   // clusters, then tiles
+    const StitchMeta *sm;      // per cluster
+    const int32_t *maps;
+    int32_t *out;
+    int32_t *hdr;
+    const StitchItem *items;
+    const WorkItem *tiles;     // the tiles' work items (block positions, capacities)
+    int32_t nitems;
+    int32_t pad;
+    int32_t *queue;
+};
+
 // Edge and triangle lists indexed by smallest vertex (original ids): edges
 // {a < b} of vertex a at eidx[2 eoff[a] .. 2 eoff[a+1]) as (b, id) sorted by
 // b; triangles {a < b < c} at fidx[4 foff[a] ..) as (b, c, id, 0) sorted by

@@ -58,7 +58,7 @@ void parallel_for(int64_t n, F f) {
 }  // namespace
 
 gale_status prepare_streams(int32_t nv, int64_t nt, const int32_t *tv, const int32_t *cl, int32_t ncl,
-                            HostStreams &out, std::string &err) {
+                            HostStreams &out, std::string &err, const std::vector<char> *keep) {
     if (nv < 0 || nt < 0 || ncl <= 0) {
         err = "nv, nt must be >= 0 and nclusters >= 1";
         return GALE_EINVAL;
@@ -299,6 +299,7 @@ gale_status prepare_streams(int32_t nv, int64_t nt, const int32_t *tv, const int
                 while (true) {
                     const int32_t k = next.fetch_add(1);
                     if (k >= ncl) break;
+                    if (keep && !(*keep)[k]) continue;  // streams of this cluster not wanted
                     auto &tab = ltab[k];
                     const int64_t s0 = soff[k], s1 = soff[k + 1];
                     const int64_t h0 = hoff[k], h1 = hoff[k + 1];
@@ -380,6 +381,7 @@ gale_status prepare_streams(int32_t nv, int64_t nt, const int32_t *tv, const int
                 while (true) {
                     const int32_t k = next.fetch_add(1);
                     if (k >= ncl) break;
+                    if (keep && !(*keep)[k]) continue;
                     const auto &tab = ltab[k];
                     const ClusterMeta &m = out.meta[k];
                     for (int32_t l = 0; l < m.L; ++l) lid[tab[l]] = l;

@@ -31,7 +31,7 @@ class GaleConfig(C.Structure):
         ("max_queue", C.c_int32), ("launch_classes", C.c_int32), ("hip_stream", C.c_void_p),
         ("global_cu_share", C.c_double), ("dev_arena", C.c_void_p), ("arena_bytes", C.c_uint64),
         ("tune_table_path", C.c_char_p), ("prefetch_depth", C.c_int32), ("front_end", C.c_int32),
-        ("simplex_lists", C.c_int32),
+        ("simplex_lists", C.c_int32), ("tile_entries", C.c_int32),
     ]
 
 
@@ -202,7 +202,7 @@ class Context:
                  lds_bytes: int = 0, max_inflight: int = 0, cache_budget_bytes: int = 0, max_queue: int = 0,
                  stream=None, launch_classes: int = 0, global_cu_share: float = 0.0, dev_arena=None,
                  arena_bytes: int = 0, tune_table_path: str | None = None, prefetch_depth: int = 0,
-                 front_end: str = "single", simplex_lists: bool = False):
+                 front_end: str = "single", simplex_lists: bool = False, tile_entries: int = 0):
         lib = load_library()
         self._lib = lib
         cfg = GaleConfig()
@@ -224,6 +224,7 @@ class Context:
         cfg.prefetch_depth = prefetch_depth
         cfg.front_end = {"single": FRONT_SINGLE, "per_relation": FRONT_PER_RELATION}[front_end]
         cfg.simplex_lists = 1 if simplex_lists else 0
+        cfg.tile_entries = int(tile_entries)
         h = C.c_void_p()
         _check(lib.gale_create(C.byref(cfg), C.byref(h)), "gale_create")
         self._h = h

@@ -78,7 +78,7 @@ def test_global_memory_path(name):
     m = SMALL[name]
     _say("global path", name)
     orc = oracle.Oracle.of(m)
-    with gale.Context(form="batched", lds_bytes=256) as ctx:
+    with gale.Context(form="batched", lds_bytes=256, tile_entries=-1) as ctx:
         ctx.load(m.tets, m.cluster, m.nclusters)
         compare_all(ctx, m, orc)
         st = ctx.stats()
@@ -119,7 +119,7 @@ def test_config1_as_one_cluster_global_path():
     m = meshgen.Mesh(tets=base.tets, cluster=np.zeros(base.nv, np.int32), nclusters=1)
     _say("config 1 as one cluster")
     orc = oracle.Oracle.of(m)
-    with gale.Context(form="batched") as ctx:
+    with gale.Context(form="batched", tile_entries=-1) as ctx:
         ctx.load(m.tets, m.cluster, m.nclusters)
         compare_all(ctx, m, orc)
 
@@ -324,7 +324,7 @@ def test_refined_lognormal_clusters(classes):
     m, orc = _refined36()
     _say("refined", m.nv, m.nt, m.nclusters, "classes", classes)
     for form in ("batched", "plain"):
-        with gale.Context(form=form, launch_classes=classes) as ctx:
+        with gale.Context(form=form, launch_classes=classes, tile_entries=-1) as ctx:
             ctx.load(m.tets, m.cluster, m.nclusters)
             compare_all(ctx, m, orc)
             st = ctx.stats()
@@ -347,7 +347,7 @@ def test_hybrid_path_small_budgets(lds):
     gale = _gale()
     m, orc = _refined36()
     _say("refined hybrid budget", lds)
-    with gale.Context(form="batched", lds_bytes=lds) as ctx:
+    with gale.Context(form="batched", lds_bytes=lds, tile_entries=-1) as ctx:
         ctx.load(m.tets, m.cluster, m.nclusters)
         compare_all(ctx, m, orc)
         compare_all(ctx, m, orc, mask=4)
@@ -426,7 +426,7 @@ def test_global_launch_on_a_share_of_the_cus(share):
     gale = _gale()
     m, orc = _refined36()
     ids = np.arange(m.nclusters, dtype=np.int32)
-    with gale.Context(form="batched", launch_classes=6, global_cu_share=share) as ctx:
+    with gale.Context(form="batched", launch_classes=6, global_cu_share=share, tile_entries=-1) as ctx:
         ctx.load(m.tets, m.cluster, m.nclusters)
         assert ctx.stats()["global_cu_share"] == share
         compare_all(ctx, m, orc)
@@ -470,7 +470,7 @@ def test_high_valence_rows(path):
         m = meshgen.Mesh(tets=m.tets, cluster=np.zeros(m.nv, np.int32), nclusters=1)
     _say("fans", path, m.nt)
     orc = oracle.Oracle.of(m)
-    kw = {"lds_bytes": 256} if path == "global" else {}
+    kw = {"lds_bytes": 256, "tile_entries": -1} if path == "global" else {}
     with gale.Context(form="plain" if path == "plain" else "batched", **kw) as ctx:
         ctx.load(m.tets, m.cluster, m.nclusters)
         compare_all(ctx, m, orc)
@@ -489,8 +489,8 @@ def test_nonmanifold_faces(path):
     m = meshgen.nonmanifold(n=8, fins=12, dups=6, nclusters=2, seed=5)
     _say("nonmanifold", path, m.nt)
     orc = oracle.Oracle.of(m)
-    kw = {"lds": {}, "hybrid": {"lds_bytes": 12288}, "global": {"lds_bytes": 12288, "launch_classes": 8},
-          "plain": {}}[path]
+    kw = {"lds": {}, "hybrid": {"lds_bytes": 12288, "tile_entries": -1},
+          "global": {"lds_bytes": 12288, "launch_classes": 8, "tile_entries": -1}, "plain": {}}[path]
     with gale.Context(form="plain" if path == "plain" else "batched", **kw) as ctx:
         ctx.load(m.tets, m.cluster, m.nclusters)
         compare_all(ctx, m, orc)
@@ -518,7 +518,8 @@ def test_face_table_overflow_doubles_passes(path, lds):
     m = meshgen.loose_tets()
     orc = oracle.Oracle.of(m)
     _say("face table overflow", path, lds)
-    with gale.Context(form="batched", lds_bytes=lds, launch_classes=16 if path == "hybrid" else 0) as ctx:
+    with gale.Context(form="batched", lds_bytes=lds, launch_classes=16 if path == "hybrid" else 0,
+                      tile_entries=-1) as ctx:
         ctx.load(m.tets, m.cluster, m.nclusters)
         compare_all(ctx, m, orc, mask=4)
         st = ctx.stats()
@@ -574,3 +575,69 @@ def test_tune_table_written_and_applied(tmp_path):
         st = ctx.stats()
         assert st["tune_applied"] == 1 and abs(st["global_cu_share"] - share) < 1e-3
         compare_all(ctx, m, orc)
+
+
+@pytest.mark.parametrize("tile", [2500, 8000, 20000])
+def test_tiled_clusters_equal_oracle(tile):
+    """Clusters too large for one workgroup's LDS built as tiles of about
+    `tile` VT entries (breadth-first groups of their vertices, each on the LDS
+    path like a cluster of its own) and assembled: every block equals the
+    oracle's, built directly and from a graph replay, for every mask."""
+    gale = _gale()
+    m, orc = _refined36()
+    ids = np.arange(m.nclusters, dtype=np.int32)
+    with gale.Context(form="batched", tile_entries=tile) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        compare_all(ctx, m, orc)
+        for mask in (1, 2, 4, 3, 6):
+            compare_all(ctx, m, orc, mask=mask)
+        st = ctx.stats()
+        _say("tiles", tile, "global", st["global_path_blocks"], "exhaustive", st["tt_exhaustive_blocks"])
+        assert st["tt_exhaustive_blocks"] == 0
+        g = ctx.graph_create(ids, 7)
+        for _ in range(2):
+            tk = ctx.graph_launch(g)
+            ctx.poll(tk)
+            bad = []
+            for k in range(m.nclusters):
+                for rel in REL:
+                    v = ctx.block_device(tk, k, rel)
+                    got = (_d2h(v.row_ids, v.nrows), _d2h(v.offsets, v.nrows + 1), _d2h(v.entries, v.nnz))
+                    if not all(np.array_equal(a, b) for a, b in zip(got, orc.block(k, rel))):
+                        bad.append((k, rel))
+            ctx.release(tk)
+            assert not bad, bad[:10]
+        ctx.graph_destroy(g)
+
+
+def test_config1_one_cluster_as_tiles():
+    """The whole 32^3 lattice as one cluster (714,984 VT entries) built as
+    tiles and assembled into one block per relation (a tile whose working set
+    still exceeds the LDS runs on the global path like a cluster)."""
+    gale = _gale()
+    base = meshgen.config(1)
+    m = meshgen.Mesh(tets=base.tets, cluster=np.zeros(base.nv, np.int32), nclusters=1)
+    orc = oracle.Oracle.of(m)
+    with gale.Context(form="batched") as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        compare_all(ctx, m, orc)
+        _say("tiles on the global path", ctx.stats()["global_path_blocks"])
+
+
+@pytest.mark.parametrize("kind", ["fans", "nonmanifold"])
+def test_tiles_of_high_valence_and_nonmanifold_clusters(kind):
+    """Tiles on closed fans (VT rows up to 1,040 entries) and on meshes with
+    faces of three tetrahedra and duplicated tetrahedra (a tile whose TT rows
+    need exhaustive pairing, or exceed their bound, makes the cluster build
+    again as a whole)."""
+    gale = _gale()
+    if kind == "fans":
+        m = meshgen.fans(seed=11)
+        m = meshgen.Mesh(tets=m.tets, cluster=np.zeros(m.nv, np.int32), nclusters=1)
+    else:
+        m = meshgen.nonmanifold(n=10, fins=20, dups=8, nclusters=2, seed=6)
+    orc = oracle.Oracle.of(m)
+    with gale.Context(form="batched", tile_entries=600) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        compare_all(ctx, m, orc)
+        compare_all(ctx, m, orc, mask=4)
