@@ -443,15 +443,19 @@ void expand_tiles(const gale_ctx *ctx, std::vector<WorkItem> &base, int64_t &wor
             out.push_back(it);
             continue;
         }
-        StitchItem si{};
-        si.out_word = it.out_word;
-        si.cluster = c;
-        si.mask = it.mask;
-        si.cap_vv = it.cap_vv;
-        si.cap_tt = it.cap_tt;
-        si.hdr_index = it.hdr_index;
-        si.tiles = (int32_t)tiles.size();
-        stitch.push_back(si);
+        // one stitch item per relation (bits 8.. of mask name it)
+        for (uint32_t rel : {kRelVT, kRelVV, kRelTT}) {
+            if (!(it.mask & rel)) continue;
+            StitchItem si{};
+            si.out_word = it.out_word;
+            si.cluster = c;
+            si.mask = it.mask | (rel << 8);
+            si.cap_vv = it.cap_vv;
+            si.cap_tt = it.cap_tt;
+            si.hdr_index = it.hdr_index;
+            si.tiles = (int32_t)tiles.size();
+            stitch.push_back(si);
+        }
         for (int32_t j = 0; j < ctx->tile_count[c]; ++j) {
             WorkItem ti{};
             ti.cluster = ctx->ncl + ctx->tile_first[c] + j;
@@ -499,7 +503,7 @@ gale_status launch_stitch_items(gale_ctx *ctx, Batch &b, const std::vector<Stitc
     a.tiles = (const WorkItem *)(d + 64 + (size_t)ns * sizeof(StitchItem));
     a.nitems = ns;
     a.queue = (int32_t *)d;
-    const int grid = std::max(1, std::min(ns, ctx->num_cus * 4));
+    const int grid = std::max(1, std::min(ns, ctx->num_cus * 8));
     e = launch_stitch(a, grid, st);
     ctx->n_launches++;
     if (e != hipSuccess) return fail(GALE_EDEVICE, std::string("stitch launch: ") + hipGetErrorString(e));

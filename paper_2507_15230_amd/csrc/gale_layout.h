@@ -145,9 +145,10 @@ struct StitchMeta {
 };
 static_assert(sizeof(StitchMeta) == 32, "StitchMeta layout");
 
-// One tiled cluster to assemble: its block (out_word, capacities, header
-// slot) and the position of its tiles' work items in the stitch launch's
-// tile table.
+// One relation of a tiled cluster to assemble: the cluster's block
+// (out_word, capacities, header slot), its relation mask (bits 0..7) and the
+// relation this item copies (bits 8..15), and the position of its tiles' work
+// items in the stitch launch's tile table.
 struct StitchItem {
     int64_t out_word;
     int32_t cluster;

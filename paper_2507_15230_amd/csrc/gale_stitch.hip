@@ -5,7 +5,9 @@
 // for the cluster's rows in ascending id, the tile and the row's index in the
 // tile's block.  One workgroup per tiled cluster: row ids copied through the
 // maps, each relation's row lengths scanned into the cluster's offsets, the
-// lists copied.  The header is the tiles' status bits and summed counts; a
+// lists copied; the relations of a cluster are separate items, so several
+// workgroups share a cluster.  The header is the tiles' status bits and
+// summed counts; a
 // tile that exceeded a capacity bound makes the cluster report it (the host
 // then builds the whole cluster again with exact capacities).
 #include <hip/hip_runtime.h>
@@ -26,11 +28,16 @@ __device__ __attribute__((always_inline)) void stitch_item(const SArgs &a, const
     __shared__ int s_status, s_nvv, s_ntt, s_nvt;
     __shared__ int64_t s_base[kMaxTiles];
     __shared__ BlockLayout s_lay[kMaxTiles];
+    // a chunk's rows: where each list starts in the tile block, and where
+    // it goes in the chunk's run of entries
+    __shared__ int64_t s_src[B];
+    __shared__ int s_pre[B];
     int sp = 0;
     const int tid = threadIdx.x;
     const ClusterMeta m = a.meta[it.cluster];
     const StitchMeta sm = a.sm[it.cluster];
-    const uint32_t mask = it.mask;
+    // the block's relations, and (bits 8..) the one this item assembles
+    const uint32_t mask = it.mask & 0xFFu, only = it.mask >> 8;
     const BlockLayout lay = block_layout(mask, m.nV, m.nT, m.nnzVT, it.cap_vv, it.cap_tt);
     int32_t *blk = a.out + it.out_word;
     if (tid == 0) {
@@ -82,11 +89,27 @@ __device__ __attribute__((always_inline)) void stitch_item(const SArgs &a, const
             if (r < n) {
                 const int32_t *tb = tile_block(j);
                 const BlockLayout &tl = s_lay[j];
-                const int o = carry + ex;
                 if (with_rows) blk[rows_dst + r] = tb[rows_at(tl) + l];
-                blk[off_dst + r] = o;
-                for (int i = 0; i < c; ++i) blk[ent_dst + o + i] = tb[ent_at(tl) + s0 + i];
+                blk[off_dst + r] = carry + ex;
+                s_src[tid] = s_base[j] + ent_at(tl) + s0;
             }
+            s_pre[tid] = r < n ? ex : tot;
+            __syncthreads();
+            // the chunk's entries, consecutive threads on consecutive output
+            // words: each finds its row by binary search over the chunk's
+            // starts (the last row starting at or before it; empty rows
+            // share their start with the next one)
+            int32_t *dst = blk + ent_dst + carry;
+            for (int e = tid; e < tot; e += B) {
+                int lo = 0, hi = B - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_pre[mid] <= e) lo = mid;
+                    else hi = mid - 1;
+                }
+                dst[e] = a.out[s_src[lo] + (e - s_pre[lo])];
+            }
+            __syncthreads();
             carry += tot;
         }
         if (tid == 0) blk[off_dst + n] = carry;
@@ -95,21 +118,22 @@ __device__ __attribute__((always_inline)) void stitch_item(const SArgs &a, const
     if (copy) {
         if (mask & (kRelVT | kRelVV)) {
             const bool vt = (mask & kRelVT) != 0;
-            if (vt)
+            if (only & kRelVT)
                 assemble(m.nV, sm.vmap_off, lay.vrows, lay.vt_off, lay.vt_ent, true,
                          [](const BlockLayout &t) { return t.vrows; }, [](const BlockLayout &t) { return t.vt_off; },
                          [](const BlockLayout &t) { return t.vt_ent; });
-            if (mask & kRelVV)
+            if (only & kRelVV)
                 assemble(m.nV, sm.vmap_off, lay.vrows, lay.vv_off, lay.vv_ent, !vt,
                          [](const BlockLayout &t) { return t.vrows; }, [](const BlockLayout &t) { return t.vv_off; },
                          [](const BlockLayout &t) { return t.vv_ent; });
         }
-        if (mask & kRelTT)
+        if (only & kRelTT)
             assemble(m.nT, sm.tmap_off, lay.trows, lay.tt_off, lay.tt_ent, true,
                      [](const BlockLayout &t) { return t.trows; }, [](const BlockLayout &t) { return t.tt_off; },
                      [](const BlockLayout &t) { return t.tt_ent; });
     }
     __syncthreads();
+    // every item of the cluster writes the same header (the tiles' status and sums)
     if (tid == 0) {
         int32_t h[8];
         h[0] = s_status;
