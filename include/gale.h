@@ -169,8 +169,9 @@ typedef struct {
     uint64_t kernel_launches;
     uint64_t overflow_reruns;       /* blocks rebuilt because a capacity bound was exceeded */
     uint64_t global_path_blocks;    /* blocks whose working set did not fit LDS */
-    uint64_t tt_exhaustive_blocks;  /* blocks whose TT face table could not pair every face (non-manifold face or
-                                       full table) and whose TT rows were built by exhaustive pairing */
+    uint64_t tt_exhaustive_blocks;  /* blocks whose TT face table could not pair every face: a non-manifold face
+                                       (TT rows then built by chains of the tetrahedra on each face) or a table
+                                       that stays full (every row against every stream tetrahedron) */
     /* serving */
     uint64_t cache_hits, cache_misses, evictions;
     uint64_t cache_bytes_resident, cache_budget;

@@ -39,9 +39,12 @@
 // pairs the two and writes each into the other's partner cell for that face.
 // The remaining stream tetrahedra then look their faces up and write
 // themselves into the internal partner's cell.  A face met a third time
-// (non-manifold) switches the cluster to exhaustive pairing.  When the table
-// is smaller than the faces, the faces are split by hash into passes.  TT
-// runs before the local VT is built and shares its LDS region.
+// (non-manifold) switches the cluster to chain pairing: the table is built
+// again with each face's internal tetrahedra linked through their partner
+// cells, and every row takes the whole chain of each of its faces (linear in
+// the stream and the entries).  When the table is smaller than the faces, the
+// faces are split by hash into passes.  TT runs before the local VT is built
+// and shares its LDS region.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <type_traits>
@@ -277,7 +280,7 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
     // faces in the table; the second to reach a face marks the partner cell of
     // the holder and its own.  Then every other stream tetrahedron looks its
     // faces up and marks the holder's cell.  A mark that finds its cell set
-    // means a third tetrahedron on one face: exhaustive pairing instead.
+    // means a third tetrahedron on one face: chain pairing instead.
     if (mask & kRelTT) {
         using CL = Cells<kL>;
         using CT = typename CL::T;
@@ -341,26 +344,35 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                     const uint32_t lm = is_low(s.x) | is_low(s.y) << 1 | is_low(s.z) << 2 | is_low(s.w) << 3;
                     todo = lm == 0u ? 0xFu : (__popc(lm) > 1 ? 0u : lm);
                 }
-                uint32_t h4[4];
+                // the faces to visit (this pass's; for lookups, those with no
+                // vertex of a lower cluster), moved to the front of a queue of
+                // (face index, current cell); the lane works on the head and
+                // shifts the queue when it is done with that face
+                int q0k = 0, q1k = 0, q2k = 0, q3k = 0;
+                uint32_t q0i = 0u, q1i = 0u, q2i = 0u, q3i = 0u;
+                int nq = 0;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     int a0, b0, c0;
                     face_of(s, k, a0, b0, c0);
-                    h4[k] = face_hash(a0, b0, c0);
-                    if (P > 1 && (int)(((h4[k] & 0xFFFFu) * (uint32_t)P) >> 16) != pass) todo &= ~(1u << k);
+                    const uint32_t h = face_hash(a0, b0, c0);
+                    const bool take =
+                        ((todo >> k) & 1u) && (P <= 1 || (int)(((h & 0xFFFFu) * (uint32_t)P) >> 16) == pass);
+                    const uint32_t i = (uint32_t)(((unsigned long long)h * (uint32_t)H) >> 32);
+                    if (take && nq == 0) { q0k = k; q0i = i; }
+                    if (take && nq == 1) { q1k = k; q1i = i; }
+                    if (take && nq == 2) { q2k = k; q2i = i; }
+                    if (take && nq == 3) { q3k = k; q3i = i; }
+                    nq += take ? 1 : 0;
                 }
-                int k = 0, fa = 0, fb = 0, fc = 0, left = 0;
-                uint32_t idx = 0u;
-                auto start = [&]() {
-                    k = __ffs(todo) - 1;
-                    face_of(s, k, fa, fb, fc);
-                    const uint32_t h = k == 0 ? h4[0] : k == 1 ? h4[1] : k == 2 ? h4[2] : h4[3];
-                    idx = (uint32_t)(((unsigned long long)h * (uint32_t)H) >> 32);
-                    left = H + 2;  // a failed swap re-reads its cell; each cell changes once
-                };
-                if (todo) start();
-                if constexpr (kH) {
-                    while (todo) {
+                int fa = 0, fb = 0, fc = 0;
+                if (nq > 0) face_of(s, q0k, fa, fb, fc);
+                int left = H + 2;  // a failed swap re-reads its cell; each cell changes once
+                while (nq > 0) {
+                    const int k = q0k;
+                    uint32_t &idx = q0i;
+                    bool stop;
+                    if constexpr (kH) {
                         const unsigned long long key = (unsigned long long)fa | (unsigned long long)fb << 15 |
                                                        (unsigned long long)fc << 30;
                         const unsigned long long w = __atomic_load_n(ht64 + idx, __ATOMIC_RELAXED);
@@ -368,7 +380,7 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                         const uint32_t c = (uint32_t)(w & 0x1FFFFull);
                         const int q = (int)c - 1;
                         const bool hit = used && (w >> 19) == key && q != p;
-                        bool stop = hit || (!used && !kIns);
+                        stop = hit || (!used && !kIns);
                         if (kIns && !used) {
                             const unsigned long long mine = (unsigned long long)(p + 1) |
                                                             (unsigned long long)k << 17 | key << 19;
@@ -380,17 +392,7 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                             if (kIns) (void)atomicAdd(win64 + 4 * (uint32_t)p + k, (1ull << 32) | (unsigned long long)c);
                         }
                         if (used && !hit) idx = idx + 1 == (uint32_t)H ? 0u : idx + 1;
-                        if (--left == 0 && !stop) {
-                            if (kIns) s_full = 1;
-                            stop = true;
-                        }
-                        if (stop) {
-                            todo &= todo - 1u;
-                            if (todo) start();
-                        }
-                    }
-                } else {
-                    while (todo) {
+                    } else {
                         uint32_t w;
                         const uint32_t c = CL::read(ht, idx, w);
                         const int q = c == 0u ? 0 : (int)c - 1;
@@ -398,7 +400,7 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                         // meets its own earlier faces on the way: skip them)
                         const int kq = face_index(tet(q), fa, fb, fc);
                         const bool hit = c != 0u && q != p && kq >= 0;
-                        bool stop = hit || (c == 0u && !kIns);
+                        stop = hit || (c == 0u && !kIns);
                         if (kIns && c == 0u) stop = CL::try_set(ht, idx, w, (uint32_t)p + 1u);
                         if (hit) {
                             // both marks issued before either old value is looked at
@@ -411,14 +413,18 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                             if (bad) s_fail = 1;
                         }
                         if (c != 0u && !hit) idx = idx + 1 == (uint32_t)H ? 0u : idx + 1;
-                        if (--left == 0 && !stop) {
-                            if (kIns) s_full = 1;
-                            stop = true;
-                        }
-                        if (stop) {
-                            todo &= todo - 1u;
-                            if (todo) start();
-                        }
+                    }
+                    if (--left == 0 && !stop) {
+                        if (kIns) s_full = 1;
+                        stop = true;
+                    }
+                    if (stop) {
+                        q0k = q1k; q0i = q1i;
+                        q1k = q2k; q1i = q2i;
+                        q2k = q3k; q2i = q3i;
+                        --nq;
+                        left = H + 2;
+                        if (nq > 0) face_of(s, q0k, fa, fb, fc);
                     }
                 }
             }
@@ -445,7 +451,7 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
             P *= 2;
             if (tid == 0) s_full = 0;
             if (P > kMaxFacePasses) {
-                if (tid == 0) s_fail = 1;
+                if (tid == 0) s_fail = 2;  // only exhaustive pairing is left
                 break;
             }
         }
@@ -476,7 +482,7 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                         for (int j = 0; j < 4; ++j)
                             x[j] = __hip_atomic_load(win64 + 4 * r + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         const bool twice = (x[0] >> 32) > 1 || (x[1] >> 32) > 1 || (x[2] >> 32) > 1 || (x[3] >> 32) > 1;
-                        if (twice) s_fail = 1;  // the rows are built again by exhaustive pairing
+                        if (twice) s_fail = 1;  // the rows are built again by chain pairing
                         w0 = twice ? 0u : (uint32_t)x[0];
                         w1 = twice ? 0u : (uint32_t)x[1];
                         w2 = twice ? 0u : (uint32_t)x[2];
@@ -517,10 +523,233 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
             }
         }
         __syncthreads();
-        if (s_fail != 0) {
-            // exhaustive pairing (non-manifold faces); rows are positions 0..nT-1
+        // Chain pairing, when a face has more than two tetrahedra (or the
+        // partner cells saw a third one): the face table is built again, the
+        // internal tetrahedra on one face forming a chain through their
+        // partner cells (the holder's cell points to the latest to arrive,
+        // which points to the one before, ...).  Every internal tetrahedron
+        // then takes as partners the whole chain of each of its faces, and
+        // every other stream tetrahedron is a partner of every tetrahedron on
+        // the chains of its faces, so the work is the stream's faces plus the
+        // entries.  A count sweep, a scan of the counts to each row's end, a
+        // scatter sweep that counts each row down to its start, and a sort of
+        // each row.  A tetrahedron with the same four vertices as the row's
+        // shares all four faces with it and is taken through face 0 only.
+        bool paired = s_fail == 0;
+        if (!paired && s_fail == 1) {
+            if (tid == 0) atomicOr(&s_status, kStTTFallback);
+            int32_t *rc = blk + lay.tt_off;  // per-row counts, then each row's end, then its start
+            int32_t *ent = blk + lay.tt_ent;
+            // chain cells: the next internal tetrahedron on the face (position + 1), 0 at the end
+            // (global cells are read past the L1 cache: other waves change them by atomics)
+            auto link_get = [&](uint32_t i) -> uint32_t {
+                if constexpr (kH)
+                    return (uint32_t)__hip_atomic_load(win64 + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                else if constexpr (kL)
+                    return CL::get(win, i);
+                else
+                    return __hip_atomic_load(win32 + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            };
+            auto rc_get = [&](int r) -> int { return __hip_atomic_load(rc + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+            auto link_exch = [&](uint32_t i, uint32_t v) -> uint32_t {
+                if constexpr (kH) {
+                    return (uint32_t)atomicExch(win64 + i, (unsigned long long)v);
+                } else if constexpr (kL) {
+                    uint32_t *wp = CL::word(win, i);
+                    const int sh = (i & 1) * 16;
+                    uint32_t w = __atomic_load_n(wp, __ATOMIC_RELAXED);
+                    while (true) {
+                        const uint32_t o = atomicCAS(wp, w, (w & ~(0xFFFFu << sh)) | (v << sh));
+                        if (o == w) return (w >> sh) & 0xFFFFu;
+                        w = o;
+                    }
+                } else {
+                    return atomicExch(win32 + i, v);
+                }
+            };
+            // a tetrahedron's own cell, empty before and written once
+            auto link_set = [&](uint32_t i, uint32_t v) {
+                if constexpr (kH) win64[i] = v;
+                else if constexpr (kL) atomicOr(CL::word(win, i), v << ((i & 1) * 16));
+                else win32[i] = v;
+            };
+            // the holder of face {fa, fb, fc} (hash h) and its face index;
+            // with ins, position p enters it as holder when the face is not
+            // in the table yet.  -1: not in the table, or (ins) table full.
+            auto find = [&](bool ins, int p, int k, int fa, int fb, int fc, uint32_t h, int &kh) -> int {
+                uint32_t idx = (uint32_t)(((unsigned long long)h * (uint32_t)H) >> 32);
+                for (int left = H; left > 0;) {
+                    if constexpr (kH) {
+                        const unsigned long long key = (unsigned long long)fa | (unsigned long long)fb << 15 |
+                                                       (unsigned long long)fc << 30;
+                        const unsigned long long w = __atomic_load_n(ht64 + idx, __ATOMIC_RELAXED);
+                        if (w == 0ull) {
+                            if (!ins) return -1;
+                            const unsigned long long mine = (unsigned long long)(p + 1) |
+                                                            (unsigned long long)k << 17 | key << 19;
+                            if (atomicCAS(ht64 + idx, 0ull, mine) == 0ull) {
+                                kh = k;
+                                return p;
+                            }
+                            continue;  // the cell was taken: read it again
+                        }
+                        if ((w >> 19) == key) {
+                            kh = (int)((w >> 17) & 3ull);
+                            return (int)(w & 0x1FFFFull) - 1;
+                        }
+                    } else {
+                        uint32_t w;
+                        const uint32_t c = CL::read(ht, idx, w);
+                        if (c == 0u) {
+                            if (!ins) return -1;
+                            if (CL::try_set(ht, idx, w, (uint32_t)p + 1u)) {
+                                kh = k;
+                                return p;
+                            }
+                            continue;  // the cell's word changed: read it again
+                        }
+                        const int q = (int)c - 1;
+                        const int kq = q < nT ? face_index(tet(q), fa, fb, fc) : -1;
+                        if (kq >= 0) {
+                            kh = kq;
+                            return q;
+                        }
+                    }
+                    idx = idx + 1 == (uint32_t)H ? 0u : idx + 1;
+                    --left;
+                }
+                if (ins) s_full = 1;
+                return -1;
+            };
+            // every internal tetrahedron on the chain of face {fa, fb, fc} from its holder
+            auto walk = [&](int u, int ku, int fa, int fb, int fc, auto &&f) {
+                for (int n = 0; n <= nT; ++n) {
+                    f(u);
+                    const uint32_t nx = link_get(4u * (uint32_t)u + (uint32_t)ku);
+                    if (nx == 0u) return;
+                    u = (int)nx - 1;
+                    ku = u < nT ? face_index(tet(u), fa, fb, fc) : -1;
+                    if (ku < 0) break;
+                }
+                atomicOr(&s_status, kStInconsistent);
+            };
+            auto emit = [&](bool scatter, int r, int u) {
+                if (!scatter) {
+                    atomicAdd(rc + r, 1);
+                } else {
+                    const int slot = atomicSub(rc + r, 1) - 1;
+                    if (slot >= 0 && slot < cap) ent[slot] = idg[u] & kIdMask;
+                }
+            };
+            auto in_pass = [&](uint32_t h, int pass, int Pc) {
+                return Pc <= 1 || (int)(((h & 0xFFFFu) * (uint32_t)Pc) >> 16) == pass;
+            };
+            auto sweep = [&](bool scatter, int Pc) {
+                for (int i = tid; i < win_words; i += B) win32[i] = 0u;
+                for (int pass = 0; pass < Pc; ++pass) {
+                    for (int i = tid; i < ht_words; i += B) ht32[i] = 0u;
+                    __syncthreads();
+                    for (int p = tid; p < nT; p += B) {
+                        const int4 s = tet(p);
+                        for (int k = 0; k < 4; ++k) {
+                            int fa, fb, fc;
+                            face_of(s, k, fa, fb, fc);
+                            const uint32_t h = face_hash(fa, fb, fc);
+                            if (!in_pass(h, pass, Pc)) continue;
+                            int kh = 0;
+                            const int q = find(true, p, k, fa, fb, fc, h, kh);
+                            if (q >= 0 && q != p)
+                                link_set(4u * (uint32_t)p + k, link_exch(4u * (uint32_t)q + kh, (uint32_t)p + 1u));
+                        }
+                    }
+                    __syncthreads();
+                    if (s_full) break;
+                    for (int p = tid; p < nT; p += B) {
+                        const int4 s = tet(p);
+                        for (int k = 0; k < 4; ++k) {
+                            int fa, fb, fc;
+                            face_of(s, k, fa, fb, fc);
+                            const uint32_t h = face_hash(fa, fb, fc);
+                            if (!in_pass(h, pass, Pc)) continue;
+                            int kh = 0;
+                            const int q = find(false, p, k, fa, fb, fc, h, kh);
+                            if (q < 0) {
+                                atomicOr(&s_status, kStInconsistent);
+                                continue;
+                            }
+                            walk(q, kh, fa, fb, fc, [&](int u) {
+                                if (u != p && (k == 0 || shared_vertices(s, tet(u)) < 4)) emit(scatter, p, u);
+                            });
+                        }
+                    }
+                    for (int p = nT + tid; p < ntot; p += B) {
+                        const int4 s = tet_global(p);
+                        const uint32_t lm = is_low(s.x) | is_low(s.y) << 1 | is_low(s.z) << 2 | is_low(s.w) << 3;
+                        const uint32_t todo = lm == 0u ? 0xFu : (__popc(lm) > 1 ? 0u : lm);
+                        for (int k = 0; k < 4; ++k) {
+                            if (!((todo >> k) & 1u)) continue;
+                            int fa, fb, fc;
+                            face_of(s, k, fa, fb, fc);
+                            const uint32_t h = face_hash(fa, fb, fc);
+                            if (!in_pass(h, pass, Pc)) continue;
+                            int kh = 0;
+                            const int q = find(false, p, k, fa, fb, fc, h, kh);
+                            if (q >= 0) walk(q, kh, fa, fb, fc, [&](int u) { emit(scatter, u, p); });
+                        }
+                    }
+                    __syncthreads();
+                }
+            };
+            int Pc = P;
+            while (Pc <= kMaxFacePasses) {
+                for (int i = tid; i < nT; i += B) rc[i] = 0;
+                if (tid == 0) s_full = 0;
+                __syncthreads();
+                sweep(false, Pc);
+                __syncthreads();
+                if (!s_full) {
+                    paired = true;
+                    break;
+                }
+                Pc *= 2;
+            }
+            if (paired) {
+                ecarry = 0;
+                for (int r0 = 0; r0 < nT; r0 += B) {
+                    const int r = r0 + tid;
+                    const int c = r < nT ? rc_get(r) : 0;
+                    int tot;
+                    const int ex = block_excl_scan<B>(c, tot, sp);
+                    if (r < nT) rc[r] = ecarry + ex + c;
+                    ecarry += tot;
+                }
+                __syncthreads();
+                sweep(true, Pc);
+                __syncthreads();
+                if (tid == 0 && s_full) atomicOr(&s_status, kStInconsistent);
+                for (int r = tid; r < nT; r += B) {
+                    const int32_t id = idg[r];
+                    if (id >= 0) atomicOr(&s_status, kStInconsistent);  // position r must be internal
+                    blk[lay.trows + r] = id & kIdMask;
+                    const int st = min(max(rc_get(r), 0), cap);
+                    const int en = max(min(r + 1 < nT ? rc_get(r + 1) : ecarry, cap), st);
+                    for (int i = st + 1; i < en; ++i) {
+                        const int32_t x = ent[i];
+                        int j = i - 1;
+                        while (j >= st && ent[j] > x) {
+                            ent[j + 1] = ent[j];
+                            --j;
+                        }
+                        ent[j + 1] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (!paired) {
+            // exhaustive pairing (a face table that stays full); rows are positions 0..nT-1
             ecarry = 0;
-            if (tid == 0) s_status |= kStTTFallback;
+            if (tid == 0) atomicOr(&s_status, kStTTFallback);
             auto tet_any = [&](int q) -> int4 { return q < nT ? tet(q) : tet_global(q); };
             for (int r0 = 0; r0 < nT; r0 += B) {
                 const int r = r0 + tid;

@@ -55,8 +55,9 @@ constexpr int kAlignWords = 32;
 constexpr int kStVVOverflow = 1;   // VV entries exceed cap_vv
 constexpr int kStTTOverflow = 2;   // TT entries exceed cap_tt
 constexpr int kStInconsistent = 4; // stream metadata disagrees with what the kernel counted
-constexpr int kStTTFallback = 8;   // face table could not pair every face (non-manifold face or full table);
-                                   // TT was built by the exhaustive path instead (informational)
+constexpr int kStTTFallback = 8;   // face table could not pair every face (non-manifold face, or a table
+                                   // that stays full); TT was built by chain pairing, or by exhaustive
+                                   // pairing for a full table (informational)
 
 struct ClusterMeta {
     int64_t tet_off;  // first stream tetrahedron of the cluster (index into tid)
@@ -274,7 +275,8 @@ struct Plan {
 GALE_HD int64_t align16(int64_t b) { return (b + 15) / 16 * 16; }
 
 // Face table passes: at most this many after doublings (then exhaustive
-// pairing); a plan starts with at most kLdsFacePasses (LDS path) or
+// pairing, every row against every stream tetrahedron); a plan starts with at
+// most kLdsFacePasses (LDS path) or
 // kHybFacePasses (hybrid path).
 constexpr int kMaxFacePasses = 32;
 constexpr int kLdsFacePasses = 8;

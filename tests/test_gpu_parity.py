@@ -482,7 +482,7 @@ def test_high_valence_rows(path):
 @pytest.mark.parametrize("path", ["lds", "hybrid", "global", "plain"])
 def test_nonmanifold_faces(path):
     """Faces of three tetrahedra (fins) and duplicated tetrahedra: the face
-    table finds them and the block's TT is built by exhaustive pairing, on the
+    table finds them and the block's TT is built by chain pairing, on the
     LDS path, the hybrid global path (non-returning marks with counts), the
     all-global path and the plain form."""
     gale = _gale()
@@ -503,6 +503,32 @@ def test_nonmanifold_faces(path):
             assert st["hybrid_path_blocks"] > 0
         if path == "global":
             assert st["global_path_blocks"] > 0 and st["hybrid_path_blocks"] == 0
+
+
+def test_large_nonmanifold_cluster_by_chains():
+    """One cluster of 358,414 tetrahedra (a 40^3 lattice with 2,000 fins and
+    500 duplicated tetrahedra, so about 2,500 faces of three or more
+    tetrahedra): the face table's chains pair it in time linear in the
+    stream and the entries.  Pairing every row against every stream
+    tetrahedron would be 1.3e11 tests on one workgroup."""
+    import time
+    gale = _gale()
+    m = meshgen.nonmanifold(n=40, fins=2000, dups=500, nclusters=1, seed=9)
+    _say("large nonmanifold cluster", m.nt)
+    orc = oracle.Oracle.of(m)
+    with gale.Context(form="batched", tile_entries=-1) as ctx:
+        ctx.load(m.tets, m.cluster, m.nclusters)
+        compare_all(ctx, m, orc, mask=4)
+        t0 = time.perf_counter()
+        tk = ctx.submit(np.zeros(1, np.int32), 4)
+        ctx.poll(tk)
+        dt = time.perf_counter() - t0
+        ctx.release(tk)
+        compare_all(ctx, m, orc)
+        st = ctx.stats()
+        _say("TT build %.3f s" % dt, "global", st["global_path_blocks"], "exhaustive", st["tt_exhaustive_blocks"])
+        assert st["tt_exhaustive_blocks"] > 0 and st["global_path_blocks"] > 0
+        assert dt < 2.0
 
 
 @pytest.mark.parametrize("path,lds", [("lds", 23964), ("hybrid", 15664)])
@@ -627,9 +653,9 @@ def test_config1_one_cluster_as_tiles():
 @pytest.mark.parametrize("kind", ["fans", "nonmanifold"])
 def test_tiles_of_high_valence_and_nonmanifold_clusters(kind):
     """Tiles on closed fans (VT rows up to 1,040 entries) and on meshes with
-    faces of three tetrahedra and duplicated tetrahedra (a tile whose TT rows
-    need exhaustive pairing, or exceed their bound, makes the cluster build
-    again as a whole)."""
+    faces of three tetrahedra and duplicated tetrahedra (tiles whose TT rows
+    are built by chain pairing; a tile whose rows exceed their bound makes the
+    cluster build again as a whole)."""
     gale = _gale()
     if kind == "fans":
         m = meshgen.fans(seed=11)
