@@ -48,6 +48,33 @@ WORKLOADS = {
        "serving with 40 consumers under 8 / 32 / 128 GB cache budgets",
 }
 COPY_BYTES = 256 << 20
+# the sources of the kernels a step runs: a committed traffic summary counts
+# only while these are unchanged
+KERNEL_SOURCES = ("gale_kernels.hip", "gale_stitch.hip", "gale_devutil.h", "gale_layout.h")
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2507_15230_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic(config_index: int):
+    """HBM bytes of one step (FETCH_SIZE + WRITE_SIZE, calibrated by a plain
+    copy) from the committed rocprofv3 summary of this workload, if it was
+    taken on the current kernel sources; else None."""
+    sha = kernel_source_sha()
+    for fn in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json"))):
+        try:
+            d = json.load(open(fn))
+        except (OSError, ValueError):
+            continue
+        if d.get("config_index") == config_index and d.get("kernel_source_sha256") == sha:
+            return d.get("traffic_bytes_per_step"), os.path.relpath(fn, ROOT)
+    return None, None
 
 
 def log(*a):
@@ -228,11 +255,13 @@ def simplices_leg(mesh, steps: int = 5) -> dict:
 
 
 def summarize_profile(out_md, title, cmd_kt, kt_dir, cmd_fetch=None, fetch_dir=None, cmd_write=None,
-                      write_dir=None, kernel_ms=None):
+                      write_dir=None, kernel_ms=None, config_index=None, alg_bytes=None):
     """Turn rocprofv3 CSV output into a committed text summary: per-kernel
     statistics, the span of each step's persistent launches (first start to
     last end, from the kernel trace), and HBM traffic per step from
-    FETCH_SIZE / WRITE_SIZE scaled by a plain copy of known size."""
+    FETCH_SIZE / WRITE_SIZE scaled by a plain copy of known size.  With
+    config_index, the traffic also goes to <out_md>_traffic.json with the hash
+    of the kernel sources, which the benchmark reads back."""
     lines = ["# " + title, "", "Command: `%s`" % cmd_kt, "", "| kernel | calls | total ms | avg us | min us | max us |",
              "|---|---|---|---|---|---|"]
     for fn in glob.glob(os.path.join(kt_dir, "**", "*kernel_stats.csv"), recursive=True):
@@ -293,6 +322,17 @@ def summarize_profile(out_md, title, cmd_kt, kt_dir, cmd_fetch=None, fetch_dir=N
             lines += ["| copy of %d MiB (%s) | | %.0f | %.0f |" % (COPY_BYTES >> 20, copy[0][:40], cf, cw), "",
                       "Scale factors (known bytes / counter): fetch %.3f, write %.3f." % (ff, wf),
                       "HBM traffic of one step (one dispatch of each persistent kernel): %.1f MB." % (tot / 1e6)]
+            if alg_bytes:
+                lines.append("Algorithmic bytes of one step: %.1f MB (traffic / algorithmic = %.3f)." % (
+                    alg_bytes / 1e6, tot / alg_bytes))
+            if config_index is not None:
+                tj = os.path.splitext(out_md)[0] + "_traffic.json"
+                with open(tj, "w") as f:
+                    json.dump({"config_index": int(config_index), "kernel_source_sha256": kernel_source_sha(),
+                               "traffic_bytes_per_step": tot, "alg_bytes_per_step": alg_bytes,
+                               "fetch_factor": ff, "write_factor": wf,
+                               "commands": [cmd_fetch, cmd_write]}, f, indent=1)
+                lines.append("Traffic record for the benchmark: `%s`." % os.path.relpath(tj, ROOT))
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("wrote", out_md)
@@ -327,12 +367,16 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one %d MiB device copy (reference for the HBM byte counters)" % (COPY_BYTES >> 20))
     ap.add_argument("--summarize-profile", nargs="+", metavar="ARG",
-                    help="OUT_MD TITLE CMD_KT KT_DIR [CMD_FETCH FETCH_DIR CMD_WRITE WRITE_DIR [KERNEL_MS]]")
+                    help="OUT_MD TITLE CMD_KT KT_DIR [CMD_FETCH FETCH_DIR CMD_WRITE WRITE_DIR [KERNEL_MS "
+                         "[CONFIG ALG_BYTES]]]")
     args = ap.parse_args()
     if args.summarize_profile:
         a = args.summarize_profile
         kms = float(a[8]) if len(a) > 8 else None
-        summarize_profile(a[0], a[1], a[2], a[3], *(a[4:8] if len(a) >= 8 else []), kernel_ms=kms)
+        cfg_i = int(a[9]) if len(a) > 10 else None
+        alg = float(a[10]) if len(a) > 10 else None
+        summarize_profile(a[0], a[1], a[2], a[3], *(a[4:8] if len(a) >= 8 else []), kernel_ms=kms,
+                          config_index=cfg_i, alg_bytes=alg)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU.  Clusters are independent, so several GPUs would each take a "
@@ -478,6 +522,7 @@ def main():
         cpu = cpu_baseline(mesh)
 
     ctx.close()
+    traffic, traffic_src = committed_traffic(args.config)
     out = {
         "metric": "VT/VV/TT relation entries/s",
         "value": value,
@@ -508,7 +553,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": traffic_src,
             "alg_bytes_per_step": int(b_alg), "alg_bytes_parts": parts, "kernel_ms": ms_kernel,
             "stream_bytes_per_step": int(b_stream),
             "stream_frac": b_stream / (ms_kernel / 1000.0) / 1e9 / HBM_PEAK_GBS,

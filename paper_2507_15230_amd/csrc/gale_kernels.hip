@@ -1074,10 +1074,18 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
         if ((mask & kRelVT) && vt_ok) {
             int32_t *buf = reinterpret_cast<int32_t *>(smem + pl.lt);
             const int bcap = kL ? (int)((pl.rix - pl.lt) / 4) : 0;
-            // a local VT entry's tetrahedron id (the hybrid path stored it)
+            // a local VT entry's tetrahedron id (the hybrid path stored it;
+            // the LDS path reads an LDS copy of the star's ids when the
+            // space after the V arrays holds one)
+            int32_t *ids_l = reinterpret_cast<int32_t *>(smem + pl.wbm);
+            const bool ids_lds = kL && (int64_t)a.lds_budget - pl.wbm >= 4 * (int64_t)ns;
+            if (ids_lds) {
+                for (int i = tid; i < ns; i += B) ids_l[i] = idg[i] & kIdMask;
+                __syncthreads();
+            }
             auto vt_key = [&](int e) -> int32_t {
                 if constexpr (kH) return lvt[e];
-                else return idg[lvt[e]] & kIdMask;
+                else return ids_lds ? ids_l[lvt[e]] : (idg[lvt[e]] & kIdMask);
             };
             // rows of at most 32 entries: one thread each, in registers, with
             // a network of 8, 16 or 32 for the wave's longest such row; longer

@@ -531,6 +531,39 @@ def test_large_nonmanifold_cluster_by_chains():
         assert dt < 2.0
 
 
+@pytest.mark.parametrize("k", [2, 40])
+def test_vv_rows_over_their_bound(k):
+    """A 14^3 lattice in four slab clusters with k tetrahedra glued to one
+    lattice vertex by that vertex alone (a bouquet: 14 + 3k neighbours from
+    24 + k tetrahedra, over the per-row bound of deg + 2 once k > 6): the LDS
+    path's provisional VV places are abandoned for the round-by-round build,
+    on every launch class."""
+    gale = _gale()
+    _, base = meshgen.kuhn_grid(14)
+    nv0 = 14 ** 3
+    v = 7 + 14 * (7 + 14 * 7)
+    extra = np.array([[v, nv0 + 3 * i, nv0 + 3 * i + 1, nv0 + 3 * i + 2] for i in range(k)], np.int32)
+    tets = np.concatenate([base, extra]).astype(np.int32)
+    rng = np.random.default_rng(3)
+    nv = nv0 + 3 * k
+    cluster = np.zeros(nv, np.int32)
+    cluster[:nv0] = np.arange(nv0) * 4 // nv0
+    cluster[nv0:] = rng.integers(0, 4, size=3 * k)
+    vperm = rng.permutation(nv).astype(np.int32)
+    tets = vperm[tets]
+    c2 = np.empty_like(cluster)
+    c2[vperm] = cluster
+    tets = tets[rng.permutation(tets.shape[0])]
+    m = meshgen.Mesh(tets=np.ascontiguousarray(tets), cluster=c2, nclusters=4)
+    _say("bouquet", k, m.nt)
+    orc = oracle.Oracle.of(m)
+    for classes in (0, 6):
+        with gale.Context(form="batched", launch_classes=classes, tile_entries=-1) as ctx:
+            ctx.load(m.tets, m.cluster, m.nclusters)
+            compare_all(ctx, m, orc)
+            compare_all(ctx, m, orc, mask=2)
+
+
 @pytest.mark.parametrize("path,lds", [("lds", 23964), ("hybrid", 15664)])
 def test_face_table_overflow_doubles_passes(path, lds):
     """Loose tetrahedra (3,900 distinct faces for 1,000 TT rows) overflow the
