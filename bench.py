@@ -314,14 +314,15 @@ def summarize_profile(out_md, title, cmd_kt, kt_dir, cmd_fetch=None, fetch_dir=N
                       "| kernel | dispatches | FETCH_SIZE KiB (mean) | WRITE_SIZE KiB (mean) |", "|---|---|---|---|"]
             tot = 0.0
             for k in sorted(per["fetch"]):
-                if "gale_persistent_kernel" not in k or k not in per["write"]:
+                if not ("gale_persistent_kernel" in k or "gale_stitch_kernel" in k) or k not in per["write"]:
                     continue
                 f, w = per["fetch"][k], per["write"][k]
                 lines.append("| %s | %d | %.0f | %.0f |" % (k[:90], len(f), sum(f) / len(f), sum(w) / len(w)))
                 tot += sum(f) / len(f) * 1024 * ff + sum(w) / len(w) * 1024 * wf
             lines += ["| copy of %d MiB (%s) | | %.0f | %.0f |" % (COPY_BYTES >> 20, copy[0][:40], cf, cw), "",
                       "Scale factors (known bytes / counter): fetch %.3f, write %.3f." % (ff, wf),
-                      "HBM traffic of one step (one dispatch of each persistent kernel): %.1f MB." % (tot / 1e6)]
+                      "HBM traffic of one step (one dispatch of each persistent kernel and of the stitch): %.1f MB."
+                      % (tot / 1e6)]
             if alg_bytes:
                 lines.append("Algorithmic bytes of one step: %.1f MB (traffic / algorithmic = %.3f)." % (
                     alg_bytes / 1e6, tot / alg_bytes))
@@ -333,6 +334,49 @@ def summarize_profile(out_md, title, cmd_kt, kt_dir, cmd_fetch=None, fetch_dir=N
                                "fetch_factor": ff, "write_factor": wf,
                                "commands": [cmd_fetch, cmd_write]}, f, indent=1)
                 lines.append("Traffic record for the benchmark: `%s`." % os.path.relpath(tj, ROOT))
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", out_md)
+
+
+def summarize_sq(out_md, title, cmd, sq_dir, kt_dir, clock_ghz=2.4, simds=1024):
+    """Committed text summary of a rocprofv3 SQ counter run: per kernel the
+    mean of each counter over its dispatches, and, with the kernel's mean
+    duration from the kernel trace in kt_dir, how busy the vector and scalar
+    issue were (a wave64 VALU instruction takes 4 cycles of a SIMD)."""
+    vals = {}
+    for fn in glob.glob(os.path.join(sq_dir, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(fn)):
+            k = r["Kernel_Name"]
+            if "gale" not in k:
+                continue
+            vals.setdefault(k, {}).setdefault(r["Counter_Name"], {}).setdefault(r["Dispatch_Id"], 0.0)
+            vals[k][r["Counter_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+    dur = {}
+    for fn in glob.glob(os.path.join(kt_dir, "**", "*kernel_stats.csv"), recursive=True):
+        for r in csv.DictReader(open(fn)):
+            dur[r["Name"]] = float(r["AverageNs"]) * 1e-9
+    lines = ["# " + title, "", "Command: `%s`" % cmd, "",
+             "Mean per dispatch; durations from the kernel trace of the same workload.", ""]
+    for k in sorted(vals):
+        c = {n: sum(d.values()) / len(d) for n, d in vals[k].items()}
+        lines += ["## " + k[:90], "", "| counter | value |", "|---|---|"]
+        lines += ["| %s | %.4g |" % (n, c[n]) for n in sorted(c)]
+        t = dur.get(k)
+        if t and c.get("SQ_INSTS_VALU"):
+            cyc = t * clock_ghz * 1e9
+            lines += ["", "Derived (mean duration %.3f ms, %d SIMDs at %.1f GHz):" % (t * 1e3, simds, clock_ghz), "",
+                      "* VALU issue: %.0f %% of the SIMDs' cycles (4 cycles per wave64 instruction)."
+                      % (100.0 * c["SQ_INSTS_VALU"] * 4 / (simds * cyc)),
+                      "* SALU issue: %.0f %% of one scalar instruction per SIMD per cycle."
+                      % (100.0 * c.get("SQ_INSTS_SALU", 0.0) / (simds * cyc)),
+                      "* LDS: %.3g instructions, %.2f bank-conflict cycles per LDS instruction."
+                      % (c.get("SQ_INSTS_LDS", 0.0), c.get("SQ_LDS_BANK_CONFLICT", 0.0) / max(1.0, c.get("SQ_INSTS_LDS", 0.0))),
+                      "* VALU / LDS / SALU instructions per wave: %.0f / %.0f / %.0f." % (
+                          c["SQ_INSTS_VALU"] / max(1.0, c.get("SQ_WAVES", 1.0)),
+                          c.get("SQ_INSTS_LDS", 0.0) / max(1.0, c.get("SQ_WAVES", 1.0)),
+                          c.get("SQ_INSTS_SALU", 0.0) / max(1.0, c.get("SQ_WAVES", 1.0)))]
+        lines.append("")
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("wrote", out_md)
@@ -366,10 +410,15 @@ def main():
     ap.add_argument("--prefetch", type=int, default=0, help="prefetch_depth of the serving leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one %d MiB device copy (reference for the HBM byte counters)" % (COPY_BYTES >> 20))
+    ap.add_argument("--summarize-sq", nargs=5, metavar=("OUT_MD", "TITLE", "CMD", "SQ_DIR", "KT_DIR"),
+                    help="summary of a rocprofv3 SQ counter run")
     ap.add_argument("--summarize-profile", nargs="+", metavar="ARG",
                     help="OUT_MD TITLE CMD_KT KT_DIR [CMD_FETCH FETCH_DIR CMD_WRITE WRITE_DIR [KERNEL_MS "
                          "[CONFIG ALG_BYTES]]]")
     args = ap.parse_args()
+    if args.summarize_sq:
+        summarize_sq(*args.summarize_sq)
+        return
     if args.summarize_profile:
         a = args.summarize_profile
         kms = float(a[8]) if len(a) > 8 else None
