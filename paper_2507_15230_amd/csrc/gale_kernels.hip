@@ -289,6 +289,8 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
         uint32_t *win32 = reinterpret_cast<uint32_t *>(win);
         uint32_t *ht32 = reinterpret_cast<uint32_t *>(ht);
         const int H = pl.H;
+        // probe positions: cells, or on the LDS path words of two cells
+        const int Hp = kL ? H / 2 : H;
         const int cap = it.cap_tt;
         const int win_words = kL ? 2 * nT : (kH ? 8 * nT : 4 * nT);  // 4 cells per row
         const int ht_words = kL ? H / 2 : (kH ? 2 * H : H);
@@ -358,7 +360,7 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                     const uint32_t h = face_hash(a0, b0, c0);
                     const bool take =
                         ((todo >> k) & 1u) && (P <= 1 || (int)(((h & 0xFFFFu) * (uint32_t)P) >> 16) == pass);
-                    const uint32_t i = (uint32_t)(((unsigned long long)h * (uint32_t)H) >> 32);
+                    const uint32_t i = (uint32_t)(((unsigned long long)h * (uint32_t)Hp) >> 32);
                     if (take && nq == 0) { q0k = k; q0i = i; }
                     if (take && nq == 1) { q1k = k; q1i = i; }
                     if (take && nq == 2) { q2k = k; q2i = i; }
@@ -367,7 +369,7 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                 }
                 int fa = 0, fb = 0, fc = 0;
                 if (nq > 0) face_of(s, q0k, fa, fb, fc);
-                int left = H + 2;  // a failed swap re-reads its cell; each cell changes once
+                int left = 2 * Hp + 2;  // a failed swap reads its cell again; each cell changes once
                 while (nq > 0) {
                     const int k = q0k;
                     uint32_t &idx = q0i;
@@ -392,6 +394,39 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                             if (kIns) (void)atomicAdd(win64 + 4 * (uint32_t)p + k, (1ull << 32) | (unsigned long long)c);
                         }
                         if (used && !hit) idx = idx + 1 == (uint32_t)H ? 0u : idx + 1;
+                    } else if constexpr (kL) {
+                        // LDS cells in pairs: a probe step reads the 32-bit
+                        // word of two cells and looks at both, the low one
+                        // first; an insert takes the first empty one, so an
+                        // empty low cell means that the face is not there
+                        uint32_t *wp = ht32 + idx;
+                        const uint32_t w = __atomic_load_n(wp, __ATOMIC_RELAXED);
+                        const uint32_t c0 = w & 0xFFFFu, c1 = w >> 16;
+                        const int q0 = c0 == 0u ? 0 : (int)c0 - 1, q1 = c1 == 0u ? 0 : (int)c1 - 1;
+                        // the holders' faces that are {fa, fb, fc}, if any (a
+                        // tetrahedron meets its own earlier faces: skip them)
+                        const int k0 = face_index(tet(q0), fa, fb, fc), k1 = face_index(tet(q1), fa, fb, fc);
+                        const bool h0 = c0 != 0u && q0 != p && k0 >= 0;
+                        const bool hit = h0 || (c1 != 0u && q1 != p && k1 >= 0);
+                        const bool room = c0 == 0u || c1 == 0u;
+                        stop = hit || (room && !kIns);
+                        if (kIns && !hit && room) {
+                            const uint32_t v = (uint32_t)p + 1u;
+                            stop = atomicCAS(wp, w, c0 == 0u ? (w | v) : (w | (v << 16))) == w;  // else: read again
+                        }
+                        if (hit) {
+                            const uint32_t c = h0 ? c0 : c1;
+                            const int q = h0 ? q0 : q1, kq = h0 ? k0 : k1;
+                            // both marks issued before either old value is looked at
+                            uint32_t o1, o2 = 0u;
+                            const uint32_t v1 = (uint32_t)p + 1u, i1 = 4 * (uint32_t)q + kq, i2 = 4 * (uint32_t)p + k;
+                            CL::mark_issue(win, i1, v1, o1);
+                            if (kIns) CL::mark_issue(win, i2, c, o2);
+                            bool bad = CL::mark_bad(i1, v1, o1);
+                            if (kIns) bad |= CL::mark_bad(i2, c, o2);
+                            if (bad) s_fail = 1;
+                        }
+                        if (!hit && !room) idx = idx + 1 == (uint32_t)Hp ? 0u : idx + 1;
                     } else {
                         uint32_t w;
                         const uint32_t c = CL::read(ht, idx, w);
@@ -423,7 +458,7 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                         q1k = q2k; q1i = q2i;
                         q2k = q3k; q2i = q3i;
                         --nq;
-                        left = H + 2;
+                        left = 2 * Hp + 2;
                         if (nq > 0) face_of(s, q0k, fa, fb, fc);
                     }
                 }
