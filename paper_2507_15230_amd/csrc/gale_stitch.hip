@@ -95,19 +95,33 @@ __device__ __attribute__((always_inline)) void stitch_item(const SArgs &a, const
             }
             s_pre[tid] = r < n ? ex : tot;
             __syncthreads();
-            // the chunk's entries, consecutive threads on consecutive output
-            // words: each finds its row by binary search over the chunk's
-            // starts (the last row starting at or before it; empty rows
-            // share their start with the next one)
+            // the chunk's entries, four consecutive words per thread and
+            // consecutive threads on consecutive runs: the row of the first
+            // word by binary search over the chunk's starts (the last row
+            // starting at or before it; empty rows share their start with
+            // the next one, rows past the chunk start at its end), the next
+            // three by stepping on; the four reads are in flight together
             int32_t *dst = blk + ent_dst + carry;
-            for (int e = tid; e < tot; e += B) {
+            for (int e0 = 4 * tid; e0 < tot; e0 += 4 * B) {
                 int lo = 0, hi = B - 1;
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
-                    if (s_pre[mid] <= e) lo = mid;
+                    if (s_pre[mid] <= e0) lo = mid;
                     else hi = mid - 1;
                 }
-                dst[e] = a.out[s_src[lo] + (e - s_pre[lo])];
+                int32_t v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0 + u;
+                    v[u] = 0;
+                    if (e < tot) {
+                        while (lo + 1 < B && s_pre[lo + 1] <= e) ++lo;
+                        v[u] = a.out[s_src[lo] + (e - s_pre[lo])];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (e0 + u < tot) dst[e0 + u] = v[u];
             }
             __syncthreads();
             carry += tot;
