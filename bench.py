@@ -281,7 +281,7 @@ def summarize_profile(out_md, title, cmd_kt, kt_dir, cmd_fetch=None, fetch_dir=N
                 if cur:
                     spans.append(cur)
                 cur = [None, None, 0]
-            elif "gale_persistent_kernel" in name and cur is not None:
+            elif ("gale_persistent_kernel" in name or "gale_stitch_kernel" in name) and cur is not None:
                 s, e = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
                 cur[0] = s if cur[0] is None else min(cur[0], s)
                 cur[1] = e if cur[1] is None else max(cur[1], e)
@@ -291,8 +291,8 @@ def summarize_profile(out_md, title, cmd_kt, kt_dir, cmd_fetch=None, fetch_dir=N
     spans = [s for s in spans if s[0] is not None]
     if spans:
         d = [(s[1] - s[0]) / 1e6 for s in spans]
-        lines += ["", "Steps (graph replays): %d; persistent launches per step: %s; span of a step's launches "
-                  "(first start to last end) mean %.3f ms, min %.3f, max %.3f." % (
+        lines += ["", "Steps (graph replays): %d; launches per step (persistent and stitch): %s; span of a step's "
+                  "launches (first start to last end) mean %.3f ms, min %.3f, max %.3f." % (
                       len(spans), sorted(set(s[2] for s in spans)), sum(d) / len(d), min(d), max(d))]
         if kernel_ms:
             lines.append("HIP events around the same launches in the benchmark's own run: %.3f ms." % kernel_ms)
