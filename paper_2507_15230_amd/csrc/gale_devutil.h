@@ -6,7 +6,48 @@
 
 namespace gale {
 // ---------------------------------------------------------------------------
-// workgroup exclusive scan (wave64 shuffles + one LDS word per wave)
+// lane exchanges within a wave by DPP (data-parallel primitives: the VALU
+// reads another lane's register directly) where a pattern exists, else by
+// the LDS crossbar (__shfl_xor).  DPP controls of the GFX9 family:
+// quad_perm(a, b, c, d) = a | b << 2 | c << 4 | d << 6, row_shl:n = 0x100 + n,
+// row_shr:n = 0x110 + n, row_ror:n = 0x120 + n (rows of 16 lanes),
+// row_bcast:15 = 0x142, row_bcast:31 = 0x143.  Every lane of the wave must
+// be active.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int dpp_xor1(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_xor2(int v) { return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_xor8(int v) { return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_xor4(int v) {
+    // lanes with bit 2 set take lane - 4 (row_shr:4), the others lane + 4 (row_shl:4)
+    const int dn = __builtin_amdgcn_mov_dpp(v, 0x114, 0xF, 0xF, false);
+    const int up = __builtin_amdgcn_mov_dpp(v, 0x104, 0xF, 0xF, false);
+    return (threadIdx.x & 4) ? dn : up;
+}
+// the value of lane ^ j (j a power of two below 64)
+__device__ __forceinline__ int lane_xor(int v, int j) {
+    switch (j) {
+        case 1: return dpp_xor1(v);
+        case 2: return dpp_xor2(v);
+        case 4: return dpp_xor4(v);
+        case 8: return dpp_xor8(v);
+        default: return __shfl_xor(v, j, 64);
+    }
+}
+
+// Inclusive sum over the lanes up to this one: shifts within rows of 16 lanes,
+// then each row's total broadcast to the rows above it.
+__device__ __forceinline__ int wave_incl_sum(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1 and 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// workgroup exclusive scan (wave64 DPP sums + one LDS word per wave)
 // ---------------------------------------------------------------------------
 // Two buffers of wave totals, used alternately (par flips on every call), so
 // that the next call may start writing while threads still read this one's.
@@ -17,12 +58,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int &total, int &par) {
     int *sw = s_wave[par];
     par ^= 1;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
+    const int x = wave_incl_sum(v);
     if (lane == 63) sw[wid] = x;
     __syncthreads();
     if (wid == 0) {
@@ -56,13 +92,7 @@ __device__ __forceinline__ int wave_sum(int x) {
 }
 
 __device__ __forceinline__ int wave_excl_scan(int v, int &total) {
-    const int lane = threadIdx.x & 63;
-    int x = v;
-    #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
+    const int x = wave_incl_sum(v);
     total = __shfl(x, 63, 64);
     return x - v;
 }
@@ -132,7 +162,7 @@ __device__ __forceinline__ void wave_bitonic(int n, const F &key, int32_t *dst) 
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const int e = lane + 64 * k;
-                    const uint32_t w = (uint32_t)__shfl_xor((int)v[k], j, 64);
+                    const uint32_t w = (uint32_t)lane_xor((int)v[k], j);
                     // the lower element of an ascending pair keeps the minimum
                     const bool keep_min = ((e & j) == 0) == ((e & s) == 0);
                     v[k] = keep_min ? min(v[k], w) : max(v[k], w);

@@ -1019,7 +1019,7 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                     }
                     int c = n;
 #pragma unroll
-                    for (int d = G / 2; d >= 1; d >>= 1) c += __shfl_xor(c, d, G);
+                    for (int d = G / 2; d >= 1; d >>= 1) c += lane_xor(c, d);
                     if (gl == 0) s_vc[par][grp] = c;
                     __syncthreads();
                     // this round's offsets: base + counts of the groups before.
@@ -1029,12 +1029,7 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                     const int a0 = lane * E < NG ? s_vc[par][lane * E] : 0;
                     const int a1 = (E == 2 && lane * E + 1 < NG) ? s_vc[par][lane * E + 1] : 0;
                     const int lsum = a0 + a1;
-                    int incl = lsum;
-#pragma unroll
-                    for (int d = 1; d < 64; d <<= 1) {
-                        const int y = __shfl_up(incl, d, 64);
-                        if (lane >= d) incl += y;
-                    }
+                    const int incl = wave_incl_sum(lsum);
                     const int src = grp / E;
                     int x = __shfl(incl - lsum, src, 64);
                     if (E == 2) {

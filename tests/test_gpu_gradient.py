@@ -16,8 +16,8 @@ pytestmark = pytest.mark.gpu
 
 
 def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+    from tests.conftest import say
+    say(*a)
 
 
 def _field(m, seed):

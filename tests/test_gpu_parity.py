@@ -20,8 +20,8 @@ def _gale():
 
 
 def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+    from tests.conftest import say
+    say(*a)
 
 
 def compare_all(ctx, mesh, orc, ids=None, mask=7, ticket=None):

@@ -21,8 +21,8 @@ def _gale():
 
 
 def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+    from tests.conftest import say
+    say(*a)
 
 
 def _expected(orc, ncl, mask):

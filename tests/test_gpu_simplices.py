@@ -22,8 +22,8 @@ def _gale():
 
 
 def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+    from tests.conftest import say
+    say(*a)
 
 
 def _compare(ctx, orc, ids, mask, form="batched"):

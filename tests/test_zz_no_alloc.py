@@ -15,8 +15,8 @@ REL = (1, 2, 4)
 
 
 def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+    from tests.conftest import say
+    say(*a)
 
 
 def _d2h(ptr, n):
