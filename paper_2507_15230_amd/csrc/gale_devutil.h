@@ -130,29 +130,31 @@ __device__ __forceinline__ void sort_regs(uint32_t (&v)[N]) {
 
 // One wave sorts a list of n keys (n wave-uniform, every lane active) and
 // writes it ascending to dst[0, n); key(i) gives the i-th key (< 2^31, all
-// distinct).  Up to 64 K keys: a bitonic network over elements e = lane + 64 k
-// (partners across lanes by shuffles for strides below 64, within a lane's
-// registers above).
+// distinct).  Up to 64 K keys: a bitonic network over elements e = K lane + k
+// (partners within a lane's registers for strides below K, across lanes by
+// lane_xor above).
 template <int K, class F>
 __device__ __forceinline__ void wave_bitonic(int n, const F &key, int32_t *dst) {
+    // lane l holds keys K l .. K l + K - 1: partners fewer than K apart are
+    // in the lane's own registers, the others K j' apart in lane l ^ j'
     const int lane = threadIdx.x & 63;
     uint32_t v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const int e = lane + 64 * k;
+        const int e = K * lane + k;
         v[k] = e < n ? (uint32_t)key(e) : 0xFFFFFFFFu;
     }
 #pragma unroll
     for (int s = 2; s <= 64 * K; s <<= 1) {
 #pragma unroll
         for (int j = s >> 1; j > 0; j >>= 1) {
-            if (j >= 64) {
-                // s >= 128: bit s of e = lane + 64 k is bit s of 64 k
+            if (j < K) {
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const int l = k ^ (j >> 6);
+                    const int l = k ^ j;
                     if (l > k) {
-                        if (((64 * k) & s) == 0)
+                        // the pair (K lane + k, K lane + l) ascends where bit s of its index is clear
+                        if (((K * lane + k) & s) == 0)
                             cswap_u(v[k], v[l]);
                         else
                             cswap_u(v[l], v[k]);
@@ -161,8 +163,8 @@ __device__ __forceinline__ void wave_bitonic(int n, const F &key, int32_t *dst) 
             } else {
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const int e = lane + 64 * k;
-                    const uint32_t w = (uint32_t)lane_xor((int)v[k], j);
+                    const int e = K * lane + k;
+                    const uint32_t w = (uint32_t)lane_xor((int)v[k], j / K);
                     // the lower element of an ascending pair keeps the minimum
                     const bool keep_min = ((e & j) == 0) == ((e & s) == 0);
                     v[k] = keep_min ? min(v[k], w) : max(v[k], w);
@@ -172,7 +174,7 @@ __device__ __forceinline__ void wave_bitonic(int n, const F &key, int32_t *dst) 
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const int e = lane + 64 * k;
+        const int e = K * lane + k;
         if (e < n) dst[e] = (int32_t)v[k];
     }
 }
