@@ -522,6 +522,13 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                         w1 = twice ? 0u : (uint32_t)x[1];
                         w2 = twice ? 0u : (uint32_t)x[2];
                         w3 = twice ? 0u : (uint32_t)x[3];
+                    } else if constexpr (kL) {
+                        // the row's four 16-bit cells in one 8-byte read
+                        const uint2 q = reinterpret_cast<const uint2 *>(win)[r];
+                        w0 = q.x & 0xFFFFu;
+                        w1 = q.x >> 16;
+                        w2 = q.y & 0xFFFFu;
+                        w3 = q.y >> 16;
                     } else {
                         w0 = CL::get(win, 4 * r);
                         w1 = CL::get(win, 4 * r + 1);
@@ -1039,15 +1046,26 @@ __device__ __attribute__((always_inline)) void build_cluster(const KArgs &a, con
                     const int round_total = __shfl(incl, 63, 64);
                     const int o_row = base_off + x;
                     par ^= 1;
+                    // each lane's place in its row: the counts of the group's
+                    // lanes before it (every lane here, so DPP row shifts serve
+                    // groups within one 16-lane row)
+                    int y = n;
+#pragma unroll
+                    for (int d = 1; d < G; d <<= 1) {
+                        int z;
+                        if constexpr (G <= 16) {
+                            z = d == 1 ? __builtin_amdgcn_update_dpp(0, y, 0x111, 0xF, 0xF, false)
+                              : d == 2 ? __builtin_amdgcn_update_dpp(0, y, 0x112, 0xF, 0xF, false)
+                              : d == 4 ? __builtin_amdgcn_update_dpp(0, y, 0x114, 0xF, 0xF, false)
+                                       : __builtin_amdgcn_update_dpp(0, y, 0x118, 0xF, 0xF, false);
+                        } else {
+                            z = __shfl_up(y, d, G);
+                        }
+                        if (gl >= d) y += z;
+                    }
                     if (r < nV) {
                         if (gl == 0) blk[lay.vv_off + r] = o_row;
                         const bool fits = o_row + c <= cap;
-                        int y = n;
-#pragma unroll
-                        for (int d = 1; d < G; d <<= 1) {
-                            const int z = __shfl_up(y, d, G);
-                            if (gl >= d) y += z;
-                        }
                         int pos = o_row + y - n;
                         if (in_regs) {
 #pragma unroll
